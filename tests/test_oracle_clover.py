@@ -1,0 +1,92 @@
+"""Pins of the oracle's clover term.
+
+* constant abelian flux B = 2 pi n/(Lx Ly) in the x-y plane, embedded as
+  diag(e^{i th}, e^{-i th}, 1): F_xy = diag(sin B, -sin B, 0), all other
+  planes zero, and eig A = {1 + kappa c_sw sin B (x4), 1 - kappa c_sw sin B (x4), 1 (x4)};
+* A = 1 for any pure-gauge field; gauge covariance A -> Omega A Omega^dag;
+* each chiral 6x6 block is Hermitian with trace exactly 6, and the blocks
+  that mix chiralities vanish."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_0910_0262_amd import synth
+
+C = torch.complex128
+
+
+@pytest.mark.parametrize("dims,n", [((4, 4, 2, 2), 1), ((6, 4, 2, 4), 2), ((8, 8, 2, 2), 3)])
+def test_abelian_flux_closed_form(dims, n):
+    lx, ly = dims[0], dims[1]
+    b = 2 * np.pi * n / (lx * ly)
+    u = torch.as_tensor(synth.abelian_flux_field(dims, n))
+    f = O.clover_field_strength(u)
+    want = torch.diag(torch.tensor([np.sin(b), -np.sin(b), 0.0], dtype=C))
+    assert torch.abs(f[(0, 1)] - want).max() < 1e-14
+    for key, val in f.items():
+        if key != (0, 1):
+            assert torch.abs(val).max() < 1e-14
+    kappa, csw = 0.13, 1.7
+    a = O.clover_matrix(u, kappa, csw)
+    ev = torch.linalg.eigvalsh(a.reshape(-1, 12, 12))
+    ref = torch.tensor(sorted([1 - kappa * csw * np.sin(b)] * 4 + [1.0] * 4 + [1 + kappa * csw * np.sin(b)] * 4),
+                       dtype=torch.float64)
+    assert torch.abs(ev - ref).max() < 1e-14
+
+
+def test_abelian_flux_u1_embedding_traceless_projection():
+    """diag(e^{i th}, 1, 1): (Q - Q^dag)/(8i) = diag(sin B, 0, 0), whose traceless part is
+    sin B diag(2/3, -1/3, -1/3); eig A = {1 -+ (2/3) k c sin B (x2 each), 1 +- (1/3) k c sin B (x4 each)}."""
+    dims = (4, 4, 2, 2)
+    b = 2 * np.pi / 16
+    u = torch.as_tensor(synth.abelian_flux_field(dims, 1, embedding="u1"))
+    f = O.clover_field_strength(u)
+    want = np.sin(b) * torch.diag(torch.tensor([2 / 3, -1 / 3, -1 / 3], dtype=C))
+    assert torch.abs(f[(0, 1)] - want).max() < 1e-14
+    kc = 0.12 * 1.3
+    a = O.clover_matrix(u, 0.12, 1.3)
+    ev = torch.linalg.eigvalsh(a.reshape(-1, 12, 12))
+    sb = np.sin(b)
+    ref = sorted([1 - 2 / 3 * kc * sb] * 2 + [1 + 2 / 3 * kc * sb] * 2 + [1 + kc * sb / 3] * 4 + [1 - kc * sb / 3] * 4)
+    assert torch.abs(ev - torch.tensor(ref, dtype=torch.float64)).max() < 1e-14
+
+
+def test_pure_gauge_clover_is_identity():
+    dims = (4, 4, 4, 4)
+    u = torch.as_tensor(synth.pure_gauge(dims, 3))
+    a = O.clover_matrix(u, 0.125, 1.0)
+    assert torch.abs(a - torch.eye(12, dtype=C)).max() < 1e-13
+
+
+def test_clover_block_invariants():
+    dims = (4, 4, 4, 4)
+    u = torch.as_tensor(synth.random_su3_field(dims, 0.5, 9))
+    a = O.clover_matrix(u, 0.124, 1.0)
+    assert torch.abs(a - a.conj().transpose(-1, -2)).max() < 1e-15
+    assert torch.abs(a[..., :6, 6:]).max() < 1e-15
+    assert torch.abs(a[..., 6:, :6]).max() < 1e-15
+    tr_up = torch.diagonal(a[..., :6, :6], dim1=-2, dim2=-1).sum(-1)
+    tr_dn = torch.diagonal(a[..., 6:, 6:], dim1=-2, dim2=-1).sum(-1)
+    assert torch.abs(tr_up - 6).max() < 1e-14 and torch.abs(tr_dn - 6).max() < 1e-14
+    ev = torch.linalg.eigvalsh(a.reshape(-1, 12, 12))
+    assert ev.min() > 0.5  # positive definite at this roughness
+
+
+def test_clover_gauge_covariance():
+    dims = (4, 4, 2, 4)
+    u = synth.random_su3_field(dims, 0.4, 21)
+    om = synth.random_su3_sites(dims, 22)
+    a = O.clover_matrix(torch.as_tensor(u), 0.12, 1.0)
+    ag = O.clover_matrix(torch.as_tensor(synth.gauge_transform(u, om)), 0.12, 1.0)
+    big = torch.kron(torch.eye(4, dtype=C), torch.eye(3, dtype=C))
+    omt = torch.as_tensor(om)
+    r = torch.einsum("st,...ab->...satb", torch.eye(4, dtype=C), omt).reshape(omt.shape[:4] + (12, 12))
+    assert big.shape == (12, 12)
+    assert torch.abs(ag - r @ a @ r.conj().transpose(-1, -2)).max() < 1e-13
+
+
+def test_clover_vanishes_when_csw_zero():
+    u = torch.as_tensor(synth.random_su3_field((4, 4, 4, 4), 0.3, 0))
+    a = O.clover_matrix(u, 0.12, 0.0)
+    assert torch.equal(a, torch.eye(12, dtype=C).expand_as(a))
