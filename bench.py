@@ -1,0 +1,281 @@
+#!/usr/bin/env python3
+"""Benchmark: CG time-to-solution (mixed vs FP64) and Mhat^dag Mhat bandwidth on one MI355X.
+
+One step is one pass of the hot path over one batch of synthetic input at
+32^3 x 64 (kappa 0.1255, c_sw 1.0, links exp(iH) with H of width 0.2): for
+each of the 8 Gaussian sources a mixed-precision solve and an FP64 solve of
+M x = b to tol 1e-10, then one fermion force with the mixed solve inside,
+then a timed run of the stencil kernels (k1, k2, Mhat^dag Mhat).  All input
+fields are resident in GPU memory before the timed region starts.
+
+Prints one JSON line on stdout; progress goes to stderr.
+
+    python bench.py [--steps K] [--warmup W] [--sources S] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "CG time-to-solution + M†M GB/s (% HBM peak), mixed vs FP64, 16^4 & 32^3x64"
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+FLOPS_PER_SITE = 1824.0  # 1320 hopping + 504 clover per site per M application
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k1_mixed_32x32x32x64.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_0910_0262_amd", "csrc", f) for f in ("qcd_device.h", "dslash.hip")]
+
+
+def log(msg: str) -> None:
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+# algorithmic bytes per even site (each field read once, neighbours counted once)
+def k1_bytes_per_site(prec: str, link_recon=12, mixed_clover=32) -> float:
+    if prec == "fp64":
+        return 192 + 8 * (16 * (6 if link_recon == 12 else 9)) + 576 + 192
+    return 52 + 8 * 24 + (288 if mixed_clover == 32 else 152) + 52
+
+
+def k2_bytes_per_site(prec: str, link_recon=12, mixed_clover=32) -> float:
+    return k1_bytes_per_site(prec, link_recon, mixed_clover) + (192 if prec == "fp64" else 52)
+
+
+def mdagm_bytes_per_site(prec: str) -> float:
+    return 2 * (k1_bytes_per_site(prec) + k2_bytes_per_site(prec))
+
+
+def traffic_for(vh: int):
+    """HBM bytes per k1 launch from the committed rocprofv3 counter summary, if it still
+    describes the current kernel source; otherwise None."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha256") != kernel_source_hash() or t.get("vh") != vh:
+        return None
+    scale = t["copy_bytes"] / ((t["copy_fetch_kib"] + t["copy_write_kib"]) * 1024.0)
+    return (t["fetch_kib"] + t["write_kib"]) * 1024.0 * scale
+
+
+def cpu_baseline(dims, kappa, csw, u_np, b_np, fp64_iters: int):
+    """The oracle as it stands, timed on the host: one Mhat^dag Mhat at the full
+    workload (the sample), scaled by the FP64 CG iteration count of the same solve."""
+    import oracle as O
+
+    t0 = time.perf_counter()
+    setup = O.CloverSetup(torch.as_tensor(u_np), kappa, csw)
+    t_setup = time.perf_counter() - t0
+    e, _ = O.to_eo(torch.as_tensor(b_np), dims)
+    t0 = time.perf_counter()
+    setup.MdagM(e)
+    t_app = time.perf_counter() - t0
+    return {
+        "value": t_app * fp64_iters,
+        "unit": "s",
+        "cores": torch.get_num_threads(),
+        "kind": "oracle",
+        "sample": (f"one oracle Mhat^dag Mhat application at {dims[0]}x{dims[1]}x{dims[2]}x{dims[3]} "
+                   f"({t_app:.2f} s, after a {t_setup:.1f} s clover setup) x {fp64_iters} FP64 CG "
+                   f"iterations of source 0 = extrapolated oracle CG time-to-solution"),
+    }
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--sources", type=int, default=8)
+    ap.add_argument("--dims", type=str, default="32,32,32,64")
+    ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--stencil-reps", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-force", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md); use --gpus 1", file=sys.stderr)
+        return 2
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 2
+
+    from paper_0910_0262_amd import Lattice, capi, synth
+
+    capi.lib()
+    dims = tuple(int(v) for v in args.dims.split(","))
+    kappa, csw, width = 0.1255, 1.0, 0.2
+    lx, ly, lz, lt = dims
+    V = lx * ly * lz * lt
+    Vh = V // 2
+    log(f"generating inputs {dims}")
+    u_np = synth.random_su3_field(dims, width, 0)
+    b_np = [synth.gaussian_source(dims, 0, k) for k in range(args.sources)]
+    xi_np = synth.heatbath_xi(dims, 0)
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    U = torch.as_tensor(u_np).to(dev)
+    B = [torch.as_tensor(b).to(dev) for b in b_np]
+    XI = torch.as_tensor(xi_np).to(dev)
+    lat = Lattice(dims, kappa, csw)
+    lat.load_gauge(U)
+    phi = lat.apply("Mhatdag", XI)
+    torch.cuda.synchronize()
+
+    # bandwidth calibration: plain copy of 2 GiB through the library's copy kernel
+    nbytes = 2 << 30
+    src = torch.empty(nbytes // 8, dtype=torch.float64, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    lat.stream_copy(dst, src)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(5):
+        lat.stream_copy(dst, src)
+    ev1.record()
+    ev1.synchronize()
+    copy_gbs = 5 * 2 * nbytes / (ev0.elapsed_time(ev1) * 1e-3) / 1e9
+    del src, dst
+    log(f"copy kernel: {copy_gbs:.0f} GB/s (read + write)")
+
+    def one_step(record):
+        for k, b in enumerate(B):
+            for prec in ("mixed", "fp64"):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                x, st = lat.solve(b, prec=prec, tol=args.tol)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                record["solves"].append({"prec": prec, "source": k, "s": dt, **st})
+                record["x"][(prec, k)] = x
+            rel = float(torch.linalg.norm(record["x"][("mixed", k)] - record["x"][("fp64", k)])
+                        / torch.linalg.norm(record["x"][("fp64", k)]))
+            record["mixed_vs_fp64"].append(rel)
+            record["x"].clear()
+        if not args.no_force:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            S, G, F, X, st = lat.action_force(phi, prec="mixed", tol=args.tol, want_X=False)
+            torch.cuda.synchronize()
+            record["force"].append({"s": time.perf_counter() - t0, "S": S, "iters": st["iters"]})
+            del G, F
+        # stencil kernels, timed with HIP events on the library's stream
+        lat.apply("MdagM", XI)
+        lat.apply("MdagM", XI, prec="mixed")
+        for prec in ("mixed", "fp64"):
+            record["stencil"][prec].append(lat.time_stencil(prec, args.stencil_reps))
+
+    def new_record():
+        return {"solves": [], "x": {}, "mixed_vs_fp64": [], "force": [], "stencil": {"mixed": [], "fp64": []}}
+
+    for w in range(args.warmup):
+        log(f"warmup step {w + 1}/{args.warmup}")
+        one_step(new_record())
+    rec = new_record()
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for s in range(args.steps):
+        one_step(rec)
+        log(f"timed step {s + 1}/{args.steps} done")
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t_start
+
+    def agg(prec, key):
+        return [r[key] for r in rec["solves"] if r["prec"] == prec]
+
+    tts = {p: float(np.mean(agg(p, "s"))) for p in ("mixed", "fp64")}
+    st_ms = {p: np.mean(np.array(rec["stencil"][p]), axis=0) for p in ("mixed", "fp64")}
+    mdagm = {}
+    for p in ("mixed", "fp64"):
+        k1_ms, k2_ms, app_ms = (float(v) for v in st_ms[p])
+        gbs = mdagm_bytes_per_site(p) * Vh / (app_ms * 1e-3) / 1e9
+        mdagm[p] = {
+            "ms": app_ms,
+            "GB_s": gbs,
+            "pct_hbm_peak": 100.0 * gbs / HBM_PEAK_GBS,
+            "pct_copy_bw": 100.0 * gbs / copy_gbs,
+            "GFLOP_s": 2 * FLOPS_PER_SITE * V / (app_ms * 1e-3) / 1e9,
+            "k1_ms": k1_ms,
+            "k2_ms": k2_ms,
+            "k1_GB_s": k1_bytes_per_site(p) * Vh / (k1_ms * 1e-3) / 1e9,
+            "k2_GB_s": k2_bytes_per_site(p) * Vh / (k2_ms * 1e-3) / 1e9,
+        }
+    k1_bytes = k1_bytes_per_site("mixed") * Vh
+    k1_ms = mdagm["mixed"]["k1_ms"]
+    achieved = k1_bytes / (k1_ms * 1e-3) / 1e9
+    traffic = traffic_for(Vh)
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                "kernel": "dslash_kernel<float, 0, true, ...> (mixed k1: t_o = A_oo^-1 H_oe p_e, binary16 "
+                          "spinors/links, FP32 clover)",
+                "bytes_per_launch": k1_bytes}
+
+    out = {
+        "metric": METRIC,
+        "value": tts["mixed"],
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * t_total / args.steps,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 (binary16 storage) + f64 reliable updates",
+        "data": "synthetic",
+        "config": {"workload": f"{lx}x{ly}x{lz}x{lt} even-odd Wilson-clover CG to tol {args.tol:g}, "
+                               f"kappa {kappa}, c_sw {csw}, SU(3) links exp(iH) width {width}, "
+                               f"{args.sources} Gaussian sources, mixed vs FP64 + force",
+                   "dims": list(dims), "sources": args.sources, "tol": args.tol},
+        "mixed_tts_s": tts["mixed"],
+        "fp64_tts_s": tts["fp64"],
+        "speedup_mixed_vs_fp64": tts["fp64"] / tts["mixed"],
+        "iters": {p: float(np.mean(agg(p, "iters"))) for p in ("mixed", "fp64")},
+        "reliable_updates_mixed": float(np.mean(agg("mixed", "reliable_updates"))),
+        "true_rel_res_max": {p: float(np.max(agg(p, "true_rel_res"))) for p in ("mixed", "fp64")},
+        "converged_all": all(r["converged"] == 1 for r in rec["solves"]),
+        "mixed_vs_fp64_rel_diff_max": float(np.max(rec["mixed_vs_fp64"])),
+        "solver_GFLOP_s": {p: float(np.mean([r["flops"] / r["s"] for r in rec["solves"] if r["prec"] == p])) / 1e9
+                           for p in ("mixed", "fp64")},
+        "mdagm": mdagm,
+        "copy_GB_s": copy_gbs,
+        "force_s": float(np.mean([f["s"] for f in rec["force"]])) if rec["force"] else None,
+        "roofline": roofline,
+        "context": "Cell/B.E. QS20 (the paper): ~10 GFLOPS and ~20 GB/s per kernel; "
+                   "8.7x / 9.6x over one 2.33 GHz Xeon core (whole application)",
+    }
+    lat.close()
+    del B, U, XI
+    if not args.no_cpu_baseline:
+        log("cpu baseline: oracle Mhat^dag Mhat at the full workload")
+        fp64_iters = int(round(np.mean([r["iters"] for r in rec["solves"]
+                                        if r["prec"] == "fp64" and r["source"] == 0])))
+        out["cpu_baseline"] = cpu_baseline(dims, kappa, csw, u_np, b_np[0], fp64_iters)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

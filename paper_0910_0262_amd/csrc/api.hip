@@ -1,0 +1,1004 @@
+// C-ABI entry points, context management and the solver drivers.
+//
+// The drivers enqueue kernels on the context's stream and keep every scalar
+// of the CG recurrence on the device (CgState).  The host keeps a few
+// iterations in flight and reads each iteration's posted state once it has
+// completed; kernels of iterations issued past convergence return at once.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "cloverqcd.h"
+#include "qcd_internal.h"
+
+using namespace qcd;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIPCHK(call)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess) return fail(QCD_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define QCHK(call)         \
+  do {                     \
+    int s_ = (call);       \
+    if (s_ != QCD_OK) return s_; \
+  } while (0)
+
+// FP64 work vectors (one checkerboard each)
+enum Slot { V_IN_E, V_IN_O, V_OUT_E, V_OUT_O, V_T, V_Q, V_X, V_R, V_P, V_RHS, V_B_E, V_B_O, V_AUX, V_Y, V_W, V_Z, NSLOT };
+// binary16 work vectors
+enum HSlot { H_P, H_T, H_Q, H_R, H_IN, H_OUT, NHSLOT };
+// ring of mailbox slots / events for the iterations in flight
+constexpr int kRing = 64;
+
+}  // namespace
+
+struct qcd_ctx {
+  int dims[4];
+  Geom g;
+  int device;
+  hipStream_t stream;
+  double kappa = 0.125, csw = 1.0;
+  int tb = -1;
+  int link_recon = 12;
+  int mixed_clover = 32;
+  int block_opt = 0;
+  bool gauge_loaded = false;
+  bool clover_ready = false;
+
+  double2* u18 = nullptr;
+  double2* u12 = nullptr;
+  uint2* uh = nullptr;
+  double2* clov = nullptr;      // A, both parities: [par][36][stride]
+  double2* clov_inv = nullptr;  // A_oo^{-1}: [36][stride]
+  float4* clov32_e = nullptr;   // A_ee in FP32
+  float4* clovinv32_o = nullptr;
+  uint4* clovh_e = nullptr;     // A_ee in binary16 + scale
+  float2* clovh_es = nullptr;
+  uint4* clovinvh_o = nullptr;
+  float2* clovinvh_os = nullptr;
+  double2* vec[NSLOT] = {};
+  uint4* hv[NHSLOT] = {};
+  float* hs[NHSLOT] = {};
+  float4* x32 = nullptr;
+  double* partial = nullptr;
+  int n_partial = 0;
+  CgState* st = nullptr;
+  CgState* st_host = nullptr;  // pinned
+  CgState* mbox_host = nullptr;  // host-mapped ring of posted states
+  CgState* mbox_dev = nullptr;   // device address of mbox_host
+  hipEvent_t ev[kRing] = {};
+  int slot_ctr = 0;
+  int* status = nullptr;
+  int* status_host = nullptr;  // pinned
+  double2* xi = nullptr;       // clover-force Xi: [par][6][9][stride]
+  double2* gint = nullptr;     // force accumulator: [mu][par][9][stride]
+  double* fbuf = nullptr;      // su(3) force [V][4][8] for the HMD step
+
+  int block() const {
+    if (block_opt) return block_opt;
+    return g.Vh >= (1 << 19) ? 256 : (g.Vh >= (1 << 16) ? 128 : 64);
+  }
+  SpF64 f64(int s) const { return SpF64{vec[s], g.stride}; }
+  SpRef ref64(int s) const { return SpRef{SP_F64, vec[s], nullptr}; }
+  SpRef refh(int s) const { return SpRef{SP_H, hv[s], hs[s]}; }
+  SpH h(int s) const { return SpH{hv[s], hs[s], g.stride}; }
+  SpF32 f32() const { return SpF32{x32, g.stride}; }
+  const void* links64() const { return link_recon == 12 ? (const void*)u12 : (const void*)u18; }
+  int lk64() const { return link_recon == 12 ? LK_F64_12 : LK_F64_18; }
+  const double2* clov_par(int par) const { return clov + (size_t)par * 36 * g.stride; }
+};
+
+namespace {
+
+template <class T>
+int dalloc(T** p, size_t bytes) {
+  if (hipMalloc((void**)p, bytes) != hipSuccess) {
+    *p = nullptr;
+    return fail(QCD_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+  }
+  return QCD_OK;
+}
+
+void free_ctx(qcd_ctx* c) {
+  auto f = [](void* p) {
+    if (p) (void)hipFree(p);
+  };
+  f(c->u18);
+  f(c->u12);
+  f(c->uh);
+  f(c->clov);
+  f(c->clov_inv);
+  f(c->clov32_e);
+  f(c->clovinv32_o);
+  f(c->clovh_e);
+  f(c->clovh_es);
+  f(c->clovinvh_o);
+  f(c->clovinvh_os);
+  for (auto* p : c->vec) f(p);
+  for (auto* p : c->hv) f(p);
+  for (auto* p : c->hs) f(p);
+  f(c->x32);
+  f(c->partial);
+  f(c->st);
+  f(c->status);
+  f(c->xi);
+  f(c->gint);
+  f(c->fbuf);
+  if (c->st_host) (void)hipHostFree(c->st_host);
+  if (c->status_host) (void)hipHostFree(c->status_host);
+  if (c->mbox_host) (void)hipHostFree(c->mbox_host);
+  for (auto& e : c->ev)
+    if (e) (void)hipEventDestroy(e);
+}
+
+int check_ctx(qcd_ctx* c) {
+  if (!c) return fail(QCD_EINVAL, "null context");
+  if (hipSetDevice(c->device) != hipSuccess) return fail(QCD_EHIP, "hipSetDevice failed");
+  return QCD_OK;
+}
+int need_gauge(qcd_ctx* c) {
+  if (!c->gauge_loaded) return fail(QCD_ESTATE, "no gauge field loaded");
+  return QCD_OK;
+}
+int need_clover(qcd_ctx* c) {
+  QCHK(need_gauge(c));
+  if (!c->clover_ready) return fail(QCD_ESTATE, "clover term not built (call qcd_build_clover or qcd_load_clover)");
+  return QCD_OK;
+}
+
+// ------------------------------------------------------------------ operator pieces
+DslashOp base_op(const qcd_ctx* c, int par_out) {
+  DslashOp op;
+  std::memset(&op, 0, sizeof(op));
+  op.par_out = par_out;
+  op.link_kind = c->lk64();
+  op.links = c->links64();
+  op.c = 1.0;
+  op.partial = c->partial;
+  return op;
+}
+
+// t_o = A_oo^{-1} g5^dag H_oe g5^dag in_e   (dag: g5 on input and output of the hop)
+int k1_f64(qcd_ctx* c, int in, int out, bool dag, const CgState* st) {
+  DslashOp op = base_op(c, 1);
+  op.in = c->ref64(in);
+  op.out = c->ref64(out);
+  op.site_mode = 0;
+  op.post = 1;
+  op.cpost = ClovRef{CL_F64, c->clov_inv, nullptr};
+  op.g5in = dag;
+  op.g5out = 0;
+  op.st = st;
+  HIPCHK(launch_dslash(c->g, op, c->block(), c->stream));
+  return QCD_OK;
+}
+// out_e = A_ee s_e - kappa^2 (g5) H_eo t_o, with epilogue
+int k2_f64(qcd_ctx* c, int site, int t, int out, bool dag, int epi, int y, double a, bool a_state,
+           const CgState* st) {
+  DslashOp op = base_op(c, 0);
+  op.in = c->ref64(t);
+  op.site = c->ref64(site);
+  op.out = c->ref64(out);
+  op.site_mode = 2;
+  op.cpre = ClovRef{CL_F64, c->clov_par(0), nullptr};
+  op.c = -c->kappa * c->kappa;
+  op.g5out = dag;
+  op.epi = epi;
+  if (epi == 2) op.y = c->ref64(y);
+  op.a = a;
+  op.a_from_state = a_state;
+  op.st = st;
+  HIPCHK(launch_dslash(c->g, op, c->block(), c->stream));
+  return QCD_OK;
+}
+// mixed-precision k1 / k2 on binary16 spinors and links, FP32 arithmetic
+ClovRef mixed_clov(const qcd_ctx* c, bool inverse_odd) {
+  if (c->mixed_clover == 16)
+    return inverse_odd ? ClovRef{CL_H, c->clovinvh_o, c->clovinvh_os} : ClovRef{CL_H, c->clovh_e, c->clovh_es};
+  return inverse_odd ? ClovRef{CL_F32, c->clovinv32_o, nullptr} : ClovRef{CL_F32, c->clov32_e, nullptr};
+}
+int k1_h(qcd_ctx* c, int in, int out, bool dag, const CgState* st) {
+  DslashOp op = base_op(c, 1);
+  op.link_kind = LK_H12;
+  op.links = c->uh;
+  op.in = c->refh(in);
+  op.out = c->refh(out);
+  op.post = 1;
+  op.cpost = mixed_clov(c, true);
+  op.g5in = dag;
+  op.st = st;
+  HIPCHK(launch_dslash(c->g, op, c->block(), c->stream));
+  return QCD_OK;
+}
+int k2_h(qcd_ctx* c, int site, int t, int out, bool dag, int epi, int y, bool a_state, const CgState* st) {
+  DslashOp op = base_op(c, 0);
+  op.link_kind = LK_H12;
+  op.links = c->uh;
+  op.in = c->refh(t);
+  op.site = c->refh(site);
+  op.out = c->refh(out);
+  op.site_mode = 2;
+  op.cpre = mixed_clov(c, false);
+  op.c = -c->kappa * c->kappa;
+  op.g5out = dag;
+  op.epi = epi;
+  if (epi == 2) op.y = c->refh(y);
+  op.a = -1.0;
+  op.a_from_state = a_state;
+  op.st = st;
+  HIPCHK(launch_dslash(c->g, op, c->block(), c->stream));
+  return QCD_OK;
+}
+// full-lattice M (or M^dag) on parity p: out_p = A_pp in_p - kappa g5 H g5 in_(1-p), with epilogue
+int m_parity(qcd_ctx* c, int par, int in_site, int in_nbr, int out, bool dag, int epi, int y, double a) {
+  DslashOp op = base_op(c, par);
+  op.in = c->ref64(in_nbr);
+  op.site = c->ref64(in_site);
+  op.out = c->ref64(out);
+  op.site_mode = 2;
+  op.cpre = ClovRef{CL_F64, c->clov_par(par), nullptr};
+  op.c = -c->kappa;
+  op.g5in = dag;
+  op.g5out = dag;
+  op.epi = epi;
+  if (epi == 2) op.y = c->ref64(y);
+  op.a = a;
+  HIPCHK(launch_dslash(c->g, op, c->block(), c->stream));
+  return QCD_OK;
+}
+
+int nblocks(const qcd_ctx* c) { return blocks_for(c->g.Vh, c->block()); }
+
+int sync_state(qcd_ctx* c) {
+  HIPCHK(hipMemcpyAsync(c->st_host, c->st, sizeof(CgState), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return QCD_OK;
+}
+
+// |x|^2 of an FP64 vector into st->scalar and returned (synchronises)
+int norm2_sync(qcd_ctx* c, int s, double* out) {
+  HIPCHK(launch_norm2(c->g, c->ref64(s), c->partial, c->block(), c->stream));
+  HIPCHK(launch_fin_scalar(c->st, c->partial, nblocks(c), c->stream));
+  QCHK(sync_state(c));
+  *out = c->st_host->scalar;
+  return QCD_OK;
+}
+
+// bytes of one Mhat^dag Mhat per even site (k1 + k2, twice), algorithmic
+double mdagm_bytes_per_site(const qcd_ctx* c, bool mixed) {
+  if (!mixed) {
+    const double sp = 192.0, lk = (c->link_recon == 12 ? 96.0 : 144.0), cl = 576.0;
+    const double k1 = sp + 8 * lk + cl + sp, k2 = k1 + sp;
+    return 2.0 * (k1 + k2);
+  }
+  const double sp = 52.0, lk = 24.0, cl = (c->mixed_clover == 16 ? 152.0 : 288.0);
+  const double k1 = sp + 8 * lk + cl + sp, k2 = k1 + sp;
+  return 2.0 * (k1 + k2);
+}
+
+// ------------------------------------------------------------------ CG drivers
+// The host keeps `depth` iterations in flight.  Each iteration ends with a
+// finalisation kernel that posts the state to a mailbox slot, followed by an
+// event; the host waits on the event of the oldest iteration in flight,
+// reads its slot, and enqueues the next iteration, so the GPU never waits for
+// the host and at most depth - 1 iterations are issued past convergence
+// (their kernels return at once).
+struct CgCounters {
+  int iters = 0, restarts = 0, ru = 0;
+  double mdagm = 0.0;  // FP64 Mhat^dag Mhat applications
+  double mdagm_mixed = 0.0;
+  double blas_bytes = 0.0;
+};
+
+struct Pipe {
+  int slot[kRing];
+  long long seq = 0, seen = 0;
+};
+
+int next_slot(qcd_ctx* c) {
+  const int s = c->slot_ctr;
+  c->slot_ctr = (c->slot_ctr + 1) % kRing;
+  return s;
+}
+
+// read the state posted in `slot` once the work before event `slot` has completed
+int wait_slot(qcd_ctx* c, int slot, CgState* out) {
+  HIPCHK(hipEventSynchronize(c->ev[slot]));
+  std::memcpy(out, (const void*)&c->mbox_host[slot], sizeof(CgState));
+  return QCD_OK;
+}
+
+int residual_f64(qcd_ctx* c, int x, int out_r, const CgState* st) {
+  // out_r = rhs - Mhat^dag Mhat x, |out_r|^2 partials
+  QCHK(k1_f64(c, x, V_T, false, st));
+  QCHK(k2_f64(c, x, V_T, V_Q, false, 0, 0, 0.0, false, st));
+  QCHK(k1_f64(c, V_Q, V_T, true, st));
+  QCHK(k2_f64(c, V_Q, V_T, out_r, true, 2, V_RHS, -1.0, false, st));
+  return QCD_OK;
+}
+
+// r = rhs - A x in FP64, posted as a reliable update (restart = 0) or a restart
+int recompute_residual(qcd_ctx* c, int restart, CgState* posted) {
+  QCHK(residual_f64(c, V_X, V_R, nullptr));
+  const int slot = next_slot(c);
+  HIPCHK(launch_fin_ru(c->st, c->partial, nblocks(c), restart, c->mbox_dev, slot, c->stream));
+  HIPCHK(hipEventRecord(c->ev[slot], c->stream));
+  if (posted) QCHK(wait_slot(c, slot, posted));
+  return QCD_OK;
+}
+
+int init_recurrence(qcd_ctx* c, double tol, double delta, int max_iter, int mixed, CgState* posted) {
+  HIPCHK(launch_norm2(c->g, c->ref64(V_RHS), c->partial, c->block(), c->stream));
+  const int slot = next_slot(c);
+  HIPCHK(launch_fin_init(c->st, c->partial, nblocks(c), tol, delta, max_iter, mixed, c->mbox_dev, slot, c->stream));
+  HIPCHK(hipEventRecord(c->ev[slot], c->stream));
+  return wait_slot(c, slot, posted);
+}
+
+int enqueue_iter_f64(qcd_ctx* c, Pipe& pp) {
+  const Geom& g = c->g;
+  const int nb = nblocks(c);
+  QCHK(k1_f64(c, V_P, V_T, false, c->st));
+  QCHK(k2_f64(c, V_P, V_T, V_Q, false, 1, 0, 0.0, false, c->st));
+  HIPCHK(launch_fin_alpha(c->st, c->partial, nb, c->stream));
+  QCHK(k1_f64(c, V_Q, V_T, true, c->st));
+  QCHK(k2_f64(c, V_Q, V_T, V_R, true, 2, V_R, 0.0, true, c->st));
+  const int slot = next_slot(c);
+  HIPCHK(launch_fin_beta(c->st, c->partial, nb, c->mbox_dev, slot, c->stream));
+  HIPCHK(launch_xp_update_f64(g, c->st, c->f64(V_X), c->f64(V_P), c->f64(V_R), c->block(), c->stream));
+  HIPCHK(hipEventRecord(c->ev[slot], c->stream));
+  pp.slot[pp.seq % kRing] = slot;
+  ++pp.seq;
+  return QCD_OK;
+}
+
+int enqueue_iter_mixed(qcd_ctx* c, Pipe& pp) {
+  const int nb = nblocks(c);
+  QCHK(k1_h(c, H_P, H_T, false, c->st));
+  QCHK(k2_h(c, H_P, H_T, H_Q, false, 1, 0, false, c->st));
+  HIPCHK(launch_fin_alpha(c->st, c->partial, nb, c->stream));
+  QCHK(k1_h(c, H_Q, H_T, true, c->st));
+  QCHK(k2_h(c, H_Q, H_T, H_R, true, 2, H_R, true, c->st));
+  const int slot = next_slot(c);
+  HIPCHK(launch_fin_beta(c->st, c->partial, nb, c->mbox_dev, slot, c->stream));
+  HIPCHK(launch_xp_update_h(c->g, c->st, c->f32(), c->h(H_P), c->h(H_R), c->block(), c->stream));
+  HIPCHK(hipEventRecord(c->ev[slot], c->stream));
+  pp.slot[pp.seq % kRing] = slot;
+  ++pp.seq;
+  return QCD_OK;
+}
+
+int pipeline_depth(const qcd_solver_params* p) { return std::min(std::max(1, p->pipeline_depth), kRing / 4); }
+
+// FP64 CG on Mhat^dag Mhat x = rhs (V_RHS) into V_X, from x = 0 or (use_x0) from V_X.
+// Work slots: V_R, V_P, V_Q, V_T.
+int cg_fp64(qcd_ctx* c, const qcd_solver_params* p, bool use_x0, CgCounters& cnt) {
+  const Geom& g = c->g;
+  const int B = c->block();
+  CgState s;
+  QCHK(init_recurrence(c, p->tol, 0.0, p->max_iter, 0, &s));
+  if (s.nan) return fail(QCD_ENAN, "non-finite right-hand side");
+  if (use_x0) {
+    QCHK(recompute_residual(c, 1, &s));
+    cnt.mdagm += 1;
+    if (s.nan) return fail(QCD_ENAN, "non-finite residual of the starting guess");
+    HIPCHK(launch_p_restart_f64(g, c->st, c->f64(V_P), c->f64(V_R), B, c->stream));
+  } else {
+    HIPCHK(launch_zero(g, c->ref64(V_X), B, c->stream));
+    HIPCHK(launch_convert(g, c->ref64(V_RHS), c->ref64(V_R), B, c->stream));
+    HIPCHK(launch_convert(g, c->ref64(V_RHS), c->ref64(V_P), B, c->stream));
+  }
+  const int depth = pipeline_depth(p);
+  int restarts = 0;
+  Pipe pp;
+  while (!s.done) {
+    while (pp.seq - pp.seen < depth) QCHK(enqueue_iter_f64(c, pp));
+    QCHK(wait_slot(c, pp.slot[pp.seen % kRing], &s));
+    ++pp.seen;
+    if (s.nan) return fail(QCD_ENAN, "non-finite residual in FP64 CG");
+    if (!s.done) continue;
+    // confirm with a recomputed residual (also after max_iter, for the stats);
+    // restart the recurrence from it if it drifted above tol
+    QCHK(recompute_residual(c, 1, &s));
+    cnt.mdagm += 1;
+    if (s.nan) return fail(QCD_ENAN, "non-finite residual in FP64 CG");
+    if (s.done || restarts >= 8) break;
+    ++restarts;
+    HIPCHK(launch_p_restart_f64(g, c->st, c->f64(V_P), c->f64(V_R), B, c->stream));
+    pp = Pipe();
+  }
+  HIPCHK(hipStreamSynchronize(c->stream));
+  *c->st_host = s;
+  cnt.iters += s.iter;
+  cnt.mdagm += s.iter;
+  cnt.restarts += restarts;
+  cnt.blas_bytes += (double)s.iter * 7.0 * 192.0 * g.Vh;
+  return QCD_OK;
+}
+
+// Mixed-precision CG with reliable updates.  Inner recurrence on binary16
+// spinors (per-site scale) and binary16 links in FP32 arithmetic, dot
+// products accumulated in FP64; x accumulates in FP32 and is folded into the
+// FP64 solution at every reliable update, where the residual is recomputed
+// with the FP64 operator and replaces the recurrence residual (p is kept).
+int cg_mixed(qcd_ctx* c, const qcd_solver_params* p, CgCounters& cnt) {
+  const Geom& g = c->g;
+  const int B = c->block();
+  CgState s;
+  QCHK(init_recurrence(c, p->tol, p->delta_reliable, p->max_iter, 1, &s));
+  if (s.nan) return fail(QCD_ENAN, "non-finite right-hand side");
+  HIPCHK(launch_zero(g, c->ref64(V_X), B, c->stream));
+  HIPCHK(launch_zero(g, SpRef{SP_F32, c->x32, nullptr}, B, c->stream));
+  HIPCHK(launch_convert(g, c->ref64(V_RHS), c->refh(H_R), B, c->stream));
+  HIPCHK(launch_convert(g, c->ref64(V_RHS), c->refh(H_P), B, c->stream));
+  const int depth = pipeline_depth(p);
+  Pipe pp;
+  long long ru_barrier = 0;  // iterations enqueued before the last reliable update
+  int ru_seen = 0, stall = 0;
+  double best_rr = s.rr_hi;
+  while (!s.done) {
+    while (pp.seq - pp.seen < depth) QCHK(enqueue_iter_mixed(c, pp));
+    QCHK(wait_slot(c, pp.slot[pp.seen % kRing], &s));
+    const long long idx = pp.seen++;
+    if (s.nan) return fail(QCD_ENAN, "non-finite residual in mixed CG");
+    if (s.done) break;
+    if (s.ru_count > ru_seen) {
+      ru_seen = s.ru_count;
+      // the FP64 residual must keep falling; otherwise finish in FP64 from x_hi
+      if (s.rr_hi < 0.5 * best_rr) {
+        best_rr = s.rr_hi;
+        stall = 0;
+      } else if (++stall >= 3) {
+        HIPCHK(hipStreamSynchronize(c->stream));
+        HIPCHK(launch_ru_accum(g, c->f64(V_X), c->f32(), B, c->stream));
+        cnt.iters += s.iter;
+        cnt.mdagm_mixed += s.iter;
+        cnt.restarts += 1;
+        qcd_solver_params q = *p;
+        q.max_iter = std::max(1, p->max_iter - s.iter);
+        return cg_fp64(c, &q, true, cnt);
+      }
+    }
+    if (s.need_ru && idx >= ru_barrier) {
+      // fold x_lo into x_hi, r = rhs - A x_hi in FP64, re-encode r; p is kept
+      HIPCHK(launch_ru_accum(g, c->f64(V_X), c->f32(), B, c->stream));
+      QCHK(recompute_residual(c, 0, nullptr));
+      HIPCHK(launch_convert(g, c->ref64(V_R), c->refh(H_R), B, c->stream));
+      cnt.mdagm += 1;
+      cnt.ru += 1;
+      ru_barrier = pp.seq;
+    }
+  }
+  HIPCHK(hipStreamSynchronize(c->stream));
+  *c->st_host = s;
+  cnt.iters += s.iter;
+  cnt.mdagm_mixed += s.iter;
+  cnt.blas_bytes += (double)s.iter * (2 * 52.0 + 3 * 52.0 + 2 * 96.0) * g.Vh;
+  return QCD_OK;
+}
+
+int run_cg(qcd_ctx* c, const qcd_solver_params* p, CgCounters& cnt) {
+  if (p->prec == QCD_MIXED) return cg_mixed(c, p, cnt);
+  return cg_fp64(c, p, false, cnt);
+}
+
+int validate_params(const qcd_solver_params* p) {
+  if (!p) return fail(QCD_EINVAL, "null solver params");
+  if (p->prec != QCD_FP64 && p->prec != QCD_MIXED) return fail(QCD_EINVAL, "prec must be QCD_FP64 or QCD_MIXED");
+  if (p->max_iter < 1) return fail(QCD_EINVAL, "max_iter must be >= 1");
+  if (p->pipeline_depth < 0) return fail(QCD_EINVAL, "pipeline_depth must be >= 0");
+  if (!(p->tol > 0.0) || !std::isfinite(p->tol)) return fail(QCD_EINVAL, "tol must be finite and > 0");
+  if (p->prec == QCD_MIXED && (!(p->delta_reliable > 0.0) || !(p->delta_reliable < 1.0)))
+    return fail(QCD_EINVAL, "delta_reliable must lie in (0, 1)");
+  return QCD_OK;
+}
+
+void fill_stats(qcd_ctx* c, const CgCounters& cnt, const qcd_solver_params* p, double seconds, double true_rel,
+                qcd_solver_stats* out) {
+  if (!out) return;
+  const CgState& s = *c->st_host;
+  out->iters = cnt.iters;
+  out->reliable_updates = cnt.ru;
+  out->restarts = cnt.restarts;
+  out->converged = s.rr_hi <= s.stop2 ? 1 : 0;
+  out->normal_rel_res = s.stop2 > 0 ? std::sqrt(s.rr_hi / (s.stop2 / (p->tol * p->tol))) : 0.0;
+  out->true_rel_res = true_rel;
+  out->seconds = seconds;
+  const double mdagm = cnt.mdagm + cnt.mdagm_mixed;
+  out->flops = mdagm * 2.0 * 1824.0 * c->g.V;
+  out->bytes = (cnt.mdagm * mdagm_bytes_per_site(c, false) + cnt.mdagm_mixed * mdagm_bytes_per_site(c, true)) *
+                   c->g.Vh +
+               cnt.blas_bytes;
+}
+
+// Solve on even sites for a prepared right-hand side in V_RHS; result in V_X.
+int solve_even(qcd_ctx* c, const qcd_solver_params* p, CgCounters& cnt) {
+  QCHK(run_cg(c, p, cnt));
+  return QCD_OK;
+}
+
+int validate_dims(const int dims[4]) {
+  if (!dims) return fail(QCD_EINVAL, "null dims");
+  long long v = 1;
+  for (int k = 0; k < 4; ++k) {
+    if (dims[k] < 2 || dims[k] % 2 != 0)
+      return fail(QCD_EINVAL, "every lattice extent must be even and >= 2 (got " + std::to_string(dims[k]) + ")");
+    v *= dims[k];
+  }
+  if (v >= (1LL << 31) / 4) return fail(QCD_EINVAL, "lattice volume too large");
+  return QCD_OK;
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+extern "C" {
+
+int qcd_version(void) { return (1 << 16) | 0; }
+
+const char* qcd_last_error(void) { return g_err.c_str(); }
+
+int qcd_create(const int dims[4], int device, uintptr_t hip_stream, qcd_ctx** out) {
+  if (!out) return fail(QCD_EINVAL, "null output pointer");
+  *out = nullptr;
+  QCHK(validate_dims(dims));
+  if (device < 0) return fail(QCD_EINVAL, "negative device index");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device >= ndev)
+    return fail(QCD_EINVAL, "device " + std::to_string(device) + " not available");
+  HIPCHK(hipSetDevice(device));
+  qcd_ctx* c = new qcd_ctx();
+  for (int k = 0; k < 4; ++k) c->dims[k] = dims[k];
+  c->device = device;
+  c->stream = (hipStream_t)hip_stream;
+  Geom& g = c->g;
+  for (int k = 0; k < 4; ++k) g.X[k] = dims[k];
+  g.Xh = dims[0] / 2;
+  g.V = dims[0] * dims[1] * dims[2] * dims[3];
+  g.Vh = g.V / 2;
+  g.stride = g.Vh;
+  g.tb = c->tb;
+  const size_t S = g.stride;
+  int rc = QCD_OK;
+  auto A = [&](auto** p, size_t bytes) {
+    if (rc == QCD_OK) rc = dalloc(p, bytes);
+  };
+  A(&c->u18, 8 * 9 * S * sizeof(double2));
+  A(&c->u12, 8 * 6 * S * sizeof(double2));
+  A(&c->uh, 8 * 3 * S * sizeof(uint2));
+  A(&c->clov, 2 * 36 * S * sizeof(double2));
+  A(&c->clov_inv, 36 * S * sizeof(double2));
+  A(&c->clov32_e, 18 * S * sizeof(float4));
+  A(&c->clovinv32_o, 18 * S * sizeof(float4));
+  A(&c->clovh_e, 9 * S * sizeof(uint4));
+  A(&c->clovh_es, S * sizeof(float2));
+  A(&c->clovinvh_o, 9 * S * sizeof(uint4));
+  A(&c->clovinvh_os, S * sizeof(float2));
+  for (int k = 0; k < NSLOT; ++k) A(&c->vec[k], 12 * S * sizeof(double2));
+  for (int k = 0; k < NHSLOT; ++k) {
+    A(&c->hv[k], 3 * S * sizeof(uint4));
+    A(&c->hs[k], S * sizeof(float));
+  }
+  A(&c->x32, 6 * S * sizeof(float4));
+  c->n_partial = g.Vh / 64 + 64;
+  A(&c->partial, (size_t)c->n_partial * sizeof(double));
+  A(&c->st, sizeof(CgState));
+  A(&c->status, sizeof(int));
+  if (rc == QCD_OK && hipHostMalloc((void**)&c->st_host, sizeof(CgState), hipHostMallocDefault) != hipSuccess)
+    rc = fail(QCD_ENOMEM, "pinned host allocation failed");
+  if (rc == QCD_OK && hipHostMalloc((void**)&c->status_host, sizeof(int), hipHostMallocDefault) != hipSuccess)
+    rc = fail(QCD_ENOMEM, "pinned host allocation failed");
+  if (rc == QCD_OK &&
+      hipHostMalloc((void**)&c->mbox_host, kRing * sizeof(CgState), hipHostMallocMapped | hipHostMallocCoherent) !=
+          hipSuccess)
+    rc = fail(QCD_ENOMEM, "pinned host allocation failed");
+  if (rc == QCD_OK && hipHostGetDevicePointer((void**)&c->mbox_dev, c->mbox_host, 0) != hipSuccess)
+    rc = fail(QCD_EHIP, "hipHostGetDevicePointer failed");
+  for (int k = 0; k < kRing && rc == QCD_OK; ++k)
+    if (hipEventCreateWithFlags(&c->ev[k], hipEventDisableTiming) != hipSuccess) rc = fail(QCD_EHIP, "hipEventCreate failed");
+  if (rc != QCD_OK) {
+    free_ctx(c);
+    delete c;
+    return rc;
+  }
+  std::memset(c->st_host, 0, sizeof(CgState));
+  std::memset(c->mbox_host, 0, kRing * sizeof(CgState));
+  *out = c;
+  return QCD_OK;
+}
+
+int qcd_destroy(qcd_ctx* c) {
+  if (!c) return QCD_OK;
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  free_ctx(c);
+  delete c;
+  return QCD_OK;
+}
+
+int qcd_set_params(qcd_ctx* c, double kappa, double csw, int t_boundary) {
+  QCHK(check_ctx(c));
+  if (!(kappa > 0.0) || !std::isfinite(kappa)) return fail(QCD_EINVAL, "kappa must be finite and > 0");
+  if (!std::isfinite(csw)) return fail(QCD_EINVAL, "c_sw must be finite");
+  if (t_boundary != 1 && t_boundary != -1) return fail(QCD_EINVAL, "t_boundary must be +1 or -1");
+  c->kappa = kappa;
+  c->csw = csw;
+  c->tb = t_boundary;
+  c->g.tb = t_boundary;
+  c->clover_ready = false;
+  return QCD_OK;
+}
+
+int qcd_set_option(qcd_ctx* c, int option, int value) {
+  QCHK(check_ctx(c));
+  switch (option) {
+    case QCD_OPT_LINK_RECON:
+      if (value != 12 && value != 18) return fail(QCD_EINVAL, "link reconstruction must be 12 or 18");
+      c->link_recon = value;
+      return QCD_OK;
+    case QCD_OPT_MIXED_CLOVER:
+      if (value != 16 && value != 32) return fail(QCD_EINVAL, "mixed clover storage must be 16 or 32");
+      c->mixed_clover = value;
+      return QCD_OK;
+    case QCD_OPT_BLOCK:
+      if (value != 0 && (value < 64 || value > 256 || value % 64 != 0))
+        return fail(QCD_EINVAL, "block size must be 0 or a multiple of 64 in [64, 256]");
+      c->block_opt = value;
+      return QCD_OK;
+    default:
+      return fail(QCD_EINVAL, "unknown option");
+  }
+}
+
+int qcd_load_gauge(qcd_ctx* c, const void* U_dev) {
+  QCHK(check_ctx(c));
+  if (!U_dev) return fail(QCD_EINVAL, "null gauge pointer");
+  HIPCHK(launch_pack_gauge(c->g, (const double2*)U_dev, c->u18, c->stream));
+  HIPCHK(launch_derive_links(c->g, c->u18, c->u12, c->uh, c->stream));
+  c->gauge_loaded = true;
+  c->clover_ready = false;
+  return QCD_OK;
+}
+
+int qcd_store_gauge(qcd_ctx* c, void* U_dev) {
+  QCHK(check_ctx(c));
+  if (!U_dev) return fail(QCD_EINVAL, "null gauge pointer");
+  QCHK(need_gauge(c));
+  HIPCHK(launch_unpack_gauge(c->g, c->u18, (double2*)U_dev, c->stream));
+  return QCD_OK;
+}
+
+static int invert_clover(qcd_ctx* c) {
+  HIPCHK(hipMemsetAsync(c->status, 0, sizeof(int), c->stream));
+  HIPCHK(launch_clover_invert(c->g, c->clov, c->clov_inv, c->clov32_e, c->clovinv32_o, c->clovh_e, c->clovh_es,
+                              c->clovinvh_o, c->clovinvh_os, c->status, c->stream));
+  HIPCHK(hipMemcpyAsync(c->status_host, c->status, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  if (*c->status_host != 0) {
+    c->clover_ready = false;
+    return fail(QCD_ECLOVER, "an odd-site clover block is not positive definite");
+  }
+  c->clover_ready = true;
+  return QCD_OK;
+}
+
+int qcd_build_clover(qcd_ctx* c) {
+  QCHK(check_ctx(c));
+  QCHK(need_gauge(c));
+  HIPCHK(launch_clover_build(c->g, c->u18, c->kappa, c->csw, c->clov, c->stream));
+  return invert_clover(c);
+}
+
+int qcd_load_clover(qcd_ctx* c, const double* A_dev) {
+  QCHK(check_ctx(c));
+  if (!A_dev) return fail(QCD_EINVAL, "null clover pointer");
+  QCHK(need_gauge(c));
+  HIPCHK(launch_pack_clover(c->g, (const double2*)A_dev, c->clov, c->stream));
+  return invert_clover(c);
+}
+
+int qcd_get_clover(qcd_ctx* c, double* A_dev, double* Ainv_dev) {
+  QCHK(check_ctx(c));
+  QCHK(need_clover(c));
+  if (A_dev) HIPCHK(launch_unpack_clover(c->g, c->clov, (double2*)A_dev, 2, 0, c->stream));
+  if (Ainv_dev) HIPCHK(launch_unpack_clover(c->g, c->clov_inv, (double2*)Ainv_dev, 1, 0, c->stream));
+  return QCD_OK;
+}
+
+int qcd_apply(qcd_ctx* c, int op, int prec, const void* in_dev, void* out_dev) {
+  QCHK(check_ctx(c));
+  if (!in_dev || !out_dev) return fail(QCD_EINVAL, "null vector pointer");
+  if (in_dev == out_dev) return fail(QCD_EINVAL, "in and out must not overlap");
+  if (op < QCD_OP_M || op > QCD_OP_MHATDAGMHAT) return fail(QCD_EINVAL, "unknown operator");
+  if (prec != QCD_FP64 && prec != QCD_MIXED) return fail(QCD_EINVAL, "unknown precision");
+  if (prec == QCD_MIXED && (op == QCD_OP_M || op == QCD_OP_MDAG))
+    return fail(QCD_EINVAL, "the full-lattice operators are FP64 only");
+  QCHK(need_clover(c));
+  const Geom& g = c->g;
+  if (op == QCD_OP_M || op == QCD_OP_MDAG) {
+    const bool dag = op == QCD_OP_MDAG;
+    HIPCHK(launch_pack_spinor_full(g, (const double2*)in_dev, c->f64(V_IN_E), c->f64(V_IN_O), c->stream));
+    QCHK(m_parity(c, 0, V_IN_E, V_IN_O, V_OUT_E, dag, 0, 0, 0.0));
+    QCHK(m_parity(c, 1, V_IN_O, V_IN_E, V_OUT_O, dag, 0, 0, 0.0));
+    HIPCHK(launch_unpack_spinor_full(g, c->f64(V_OUT_E), c->f64(V_OUT_O), (double2*)out_dev, c->stream));
+    return QCD_OK;
+  }
+  HIPCHK(launch_pack_spinor_cb(g, (const double2*)in_dev, c->f64(V_IN_E), c->stream));
+  const bool first = op == QCD_OP_MHAT || op == QCD_OP_MHATDAGMHAT;
+  const bool second = op == QCD_OP_MHATDAG || op == QCD_OP_MHATDAGMHAT;
+  if (prec == QCD_FP64) {
+    int cur = V_IN_E;
+    if (first) {
+      QCHK(k1_f64(c, cur, V_T, false, nullptr));
+      QCHK(k2_f64(c, cur, V_T, V_OUT_E, false, 0, 0, 0.0, false, nullptr));
+      cur = V_OUT_E;
+    }
+    if (second) {
+      const int dst = cur == V_OUT_E ? V_AUX : V_OUT_E;
+      QCHK(k1_f64(c, cur, V_T, true, nullptr));
+      QCHK(k2_f64(c, cur, V_T, dst, true, 0, 0, 0.0, false, nullptr));
+      cur = dst;
+    }
+    HIPCHK(launch_unpack_spinor_cb(g, c->f64(cur), (double2*)out_dev, c->stream));
+    return QCD_OK;
+  }
+  HIPCHK(launch_convert(g, c->ref64(V_IN_E), c->refh(H_IN), c->block(), c->stream));
+  int cur = H_IN;
+  if (first) {
+    QCHK(k1_h(c, cur, H_T, false, nullptr));
+    QCHK(k2_h(c, cur, H_T, H_OUT, false, 0, 0, false, nullptr));
+    cur = H_OUT;
+  }
+  if (second) {
+    const int dst = cur == H_OUT ? H_Q : H_OUT;
+    QCHK(k1_h(c, cur, H_T, true, nullptr));
+    QCHK(k2_h(c, cur, H_T, dst, true, 0, 0, false, nullptr));
+    cur = dst;
+  }
+  HIPCHK(launch_convert(g, c->refh(cur), c->ref64(V_OUT_E), c->block(), c->stream));
+  HIPCHK(launch_unpack_spinor_cb(g, c->f64(V_OUT_E), (double2*)out_dev, c->stream));
+  return QCD_OK;
+}
+
+int qcd_solve(qcd_ctx* c, const qcd_solver_params* p, const void* b_dev, void* x_dev, qcd_solver_stats* stats) {
+  QCHK(check_ctx(c));
+  QCHK(validate_params(p));
+  if (!b_dev || !x_dev) return fail(QCD_EINVAL, "null vector pointer");
+  QCHK(need_clover(c));
+  const auto t0 = std::chrono::steady_clock::now();
+  const Geom& g = c->g;
+  const int B = c->block(), nb = nblocks(c);
+  // b -> (b_e, b_o); bhat = b_e + kappa H_eo A_oo^{-1} b_o; rhs = Mhat^dag bhat
+  HIPCHK(launch_pack_spinor_full(g, (const double2*)b_dev, c->f64(V_B_E), c->f64(V_B_O), c->stream));
+  HIPCHK(launch_clover_apply(g, c->f64(V_B_O), c->f64(V_T), c->clov_inv, c->stream));
+  {
+    DslashOp op = base_op(c, 0);
+    op.in = c->ref64(V_T);
+    op.site = c->ref64(V_B_E);
+    op.out = c->ref64(V_AUX);
+    op.site_mode = 1;
+    op.c = c->kappa;
+    HIPCHK(launch_dslash(g, op, B, c->stream));
+  }
+  QCHK(k1_f64(c, V_AUX, V_T, true, nullptr));
+  QCHK(k2_f64(c, V_AUX, V_T, V_RHS, true, 0, 0, 0.0, false, nullptr));
+  CgCounters cnt;
+  int rc = solve_even(c, p, cnt);
+  if (rc != QCD_OK && rc != QCD_ENOCONV) return rc;
+  CgState s_end = *c->st_host;
+  // x_o = A_oo^{-1} (b_o + kappa H_oe x_e)
+  {
+    DslashOp op = base_op(c, 1);
+    op.in = c->ref64(V_X);
+    op.site = c->ref64(V_B_O);
+    op.out = c->ref64(V_OUT_O);
+    op.site_mode = 1;
+    op.post = 1;
+    op.cpost = ClovRef{CL_F64, c->clov_inv, nullptr};
+    op.c = c->kappa;
+    HIPCHK(launch_dslash(g, op, B, c->stream));
+  }
+  HIPCHK(launch_unpack_spinor_full(g, c->f64(V_X), c->f64(V_OUT_O), (double2*)x_dev, c->stream));
+  // true residual ||b - M x|| / ||b|| on the full lattice
+  double rn = 0.0, bn = 0.0, t;
+  QCHK(m_parity(c, 0, V_X, V_OUT_O, V_AUX, false, 2, V_B_E, -1.0));
+  HIPCHK(launch_fin_scalar(c->st, c->partial, nb, c->stream));
+  QCHK(sync_state(c));
+  rn += c->st_host->scalar;
+  QCHK(m_parity(c, 1, V_OUT_O, V_X, V_AUX, false, 2, V_B_O, -1.0));
+  HIPCHK(launch_fin_scalar(c->st, c->partial, nb, c->stream));
+  QCHK(sync_state(c));
+  rn += c->st_host->scalar;
+  QCHK(norm2_sync(c, V_B_E, &t));
+  bn += t;
+  QCHK(norm2_sync(c, V_B_O, &t));
+  bn += t;
+  const double seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  *c->st_host = s_end;
+  fill_stats(c, cnt, p, seconds, bn > 0 ? std::sqrt(rn / bn) : 0.0, stats);
+  if (s_end.rr_hi > s_end.stop2) return fail(QCD_ENOCONV, "solver reached max_iter without meeting tol");
+  return QCD_OK;
+}
+
+// Force pipeline on the current context state; phi in V_RHS (even sites).
+static int force_core(qcd_ctx* c, const qcd_solver_params* p, double* S, CgCounters& cnt, int* conv_rc) {
+  const Geom& g = c->g;
+  const int nb = nblocks(c);
+  if (!c->xi) QCHK(dalloc(&c->xi, (size_t)2 * 6 * 9 * g.stride * sizeof(double2)));
+  if (!c->gint) QCHK(dalloc(&c->gint, (size_t)8 * 9 * g.stride * sizeof(double2)));
+  // keep phi: the solver overwrites work slots but not V_RHS
+  int rc = run_cg(c, p, cnt);
+  if (rc != QCD_OK) return rc;
+  *conv_rc = c->st_host->rr_hi <= c->st_host->stop2 ? QCD_OK : QCD_ENOCONV;
+  CgState s_end = *c->st_host;
+  // S = Re phi^dag X
+  HIPCHK(launch_dot_re(g, c->f64(V_RHS), c->f64(V_X), c->partial, c->block(), c->stream));
+  HIPCHK(launch_fin_scalar(c->st, c->partial, nb, c->stream));
+  QCHK(sync_state(c));
+  if (S) *S = c->st_host->scalar;
+  *c->st_host = s_end;
+  // Z = A_oo^{-1} H_oe X; Y = Mhat X; W = A_oo^{-1} g5 H_oe g5 Y
+  QCHK(k1_f64(c, V_X, V_Z, false, nullptr));
+  QCHK(k2_f64(c, V_X, V_Z, V_Y, false, 0, 0, 0.0, false, nullptr));
+  {
+    DslashOp op = base_op(c, 1);
+    op.in = c->ref64(V_Y);
+    op.out = c->ref64(V_W);
+    op.post = 1;
+    op.cpost = ClovRef{CL_F64, c->clov_inv, nullptr};
+    op.g5in = 1;
+    op.g5out = 1;
+    HIPCHK(launch_dslash(g, op, c->block(), c->stream));
+  }
+  const double k2 = c->kappa * c->kappa;
+  HIPCHK(launch_force_hop(g, c->u18, c->f64(V_Y), c->f64(V_W), c->f64(V_X), c->f64(V_Z), 2.0 * k2, c->gint,
+                          c->stream));
+  if (c->csw != 0.0) {
+    HIPCHK(launch_clover_xi(g, c->f64(V_Y), c->f64(V_W), c->f64(V_X), c->f64(V_Z), 1.0, k2, c->xi, c->stream));
+    HIPCHK(launch_force_clover(g, c->u18, c->xi, 0.5 * c->kappa * c->csw, c->gint, c->stream));
+  }
+  return QCD_OK;
+}
+
+int qcd_action_force(qcd_ctx* c, const qcd_solver_params* p, const void* phi_dev, double* S, void* G_dev,
+                     double* F_dev, void* X_dev, qcd_solver_stats* stats) {
+  QCHK(check_ctx(c));
+  QCHK(validate_params(p));
+  if (!phi_dev || !G_dev) return fail(QCD_EINVAL, "null pointer (phi and G are required)");
+  QCHK(need_clover(c));
+  const auto t0 = std::chrono::steady_clock::now();
+  HIPCHK(launch_pack_spinor_cb(c->g, (const double2*)phi_dev, c->f64(V_RHS), c->stream));
+  CgCounters cnt;
+  int conv = QCD_OK;
+  QCHK(force_core(c, p, S, cnt, &conv));
+  HIPCHK(launch_force_out(c->g, c->u18, c->gint, (double2*)G_dev, F_dev, c->stream));
+  if (X_dev) HIPCHK(launch_unpack_spinor_cb(c->g, c->f64(V_X), (double2*)X_dev, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  const double seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  fill_stats(c, cnt, p, seconds, -1.0, stats);
+  if (conv != QCD_OK) return fail(QCD_ENOCONV, "force solve reached max_iter without meeting tol");
+  return QCD_OK;
+}
+
+int qcd_hmd_step(qcd_ctx* c, double dt, void* U_dev, double* P_dev, const void* xi_dev,
+                 const qcd_solver_params* p, double* S, qcd_solver_stats* stats) {
+  QCHK(check_ctx(c));
+  QCHK(validate_params(p));
+  if (!U_dev || !P_dev || !xi_dev) return fail(QCD_EINVAL, "null pointer");
+  if (!std::isfinite(dt)) return fail(QCD_EINVAL, "dt must be finite");
+  const auto t0 = std::chrono::steady_clock::now();
+  const Geom& g = c->g;
+  if (!c->fbuf) QCHK(dalloc(&c->fbuf, (size_t)32 * g.V * sizeof(double)));
+  if (!c->gint) QCHK(dalloc(&c->gint, (size_t)8 * 9 * g.stride * sizeof(double2)));
+  // U_1/2 = exp(i dt/2 P) U
+  HIPCHK(launch_pack_gauge(g, (const double2*)U_dev, c->u18, c->stream));
+  HIPCHK(launch_link_exp(g, c->u18, P_dev, 0.5 * dt, c->stream));
+  HIPCHK(launch_derive_links(g, c->u18, c->u12, c->uh, c->stream));
+  c->gauge_loaded = true;
+  QCHK(qcd_build_clover(c));
+  // phi = Mhat^dag xi
+  HIPCHK(launch_pack_spinor_cb(g, (const double2*)xi_dev, c->f64(V_IN_E), c->stream));
+  QCHK(k1_f64(c, V_IN_E, V_T, true, nullptr));
+  QCHK(k2_f64(c, V_IN_E, V_T, V_RHS, true, 0, 0, 0.0, false, nullptr));
+  CgCounters cnt;
+  int conv = QCD_OK;
+  QCHK(force_core(c, p, S, cnt, &conv));
+  HIPCHK(launch_force_out(g, c->u18, c->gint, nullptr, c->fbuf, c->stream));
+  // P <- P - dt F;  U <- exp(i dt/2 P) U_1/2
+  HIPCHK(launch_mom_update(g, P_dev, c->fbuf, dt, c->stream));
+  HIPCHK(launch_link_exp(g, c->u18, P_dev, 0.5 * dt, c->stream));
+  HIPCHK(launch_derive_links(g, c->u18, c->u12, c->uh, c->stream));
+  HIPCHK(launch_unpack_gauge(g, c->u18, (double2*)U_dev, c->stream));
+  QCHK(qcd_build_clover(c));
+  const double seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  fill_stats(c, cnt, p, seconds, -1.0, stats);
+  if (conv != QCD_OK) return fail(QCD_ENOCONV, "force solve reached max_iter without meeting tol");
+  return QCD_OK;
+}
+
+int qcd_time_stencil(qcd_ctx* c, int prec, int n, double* ms) {
+  QCHK(check_ctx(c));
+  if (!ms) return fail(QCD_EINVAL, "null output pointer");
+  if (n < 1) return fail(QCD_EINVAL, "n must be >= 1");
+  if (prec != QCD_FP64 && prec != QCD_MIXED) return fail(QCD_EINVAL, "unknown precision");
+  QCHK(need_clover(c));
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(QCD_EHIP, "hipEventCreate failed");
+  }
+  int rc = QCD_OK;
+  auto timed = [&](auto&& body, double* out) -> int {
+    if (hipEventRecord(e0, c->stream) != hipSuccess) return fail(QCD_EHIP, "hipEventRecord failed");
+    for (int k = 0; k < n; ++k) QCHK(body());
+    if (hipEventRecord(e1, c->stream) != hipSuccess) return fail(QCD_EHIP, "hipEventRecord failed");
+    if (hipEventSynchronize(e1) != hipSuccess) return fail(QCD_EHIP, "hipEventSynchronize failed");
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, e0, e1) != hipSuccess) return fail(QCD_EHIP, "hipEventElapsedTime failed");
+    *out = double(t) / n;
+    return QCD_OK;
+  };
+  if (prec == QCD_FP64) {
+    if (rc == QCD_OK) rc = timed([&] { return k1_f64(c, V_IN_E, V_T, false, nullptr); }, &ms[0]);
+    if (rc == QCD_OK) rc = timed([&] { return k2_f64(c, V_IN_E, V_T, V_OUT_E, false, 0, 0, 0.0, false, nullptr); }, &ms[1]);
+    if (rc == QCD_OK)
+      rc = timed(
+          [&] {
+            QCHK(k1_f64(c, V_IN_E, V_T, false, nullptr));
+            QCHK(k2_f64(c, V_IN_E, V_T, V_OUT_E, false, 0, 0, 0.0, false, nullptr));
+            QCHK(k1_f64(c, V_OUT_E, V_T, true, nullptr));
+            return k2_f64(c, V_OUT_E, V_T, V_AUX, true, 0, 0, 0.0, false, nullptr);
+          },
+          &ms[2]);
+  } else {
+    if (rc == QCD_OK) rc = timed([&] { return k1_h(c, H_IN, H_T, false, nullptr); }, &ms[0]);
+    if (rc == QCD_OK) rc = timed([&] { return k2_h(c, H_IN, H_T, H_OUT, false, 0, 0, false, nullptr); }, &ms[1]);
+    if (rc == QCD_OK)
+      rc = timed(
+          [&] {
+            QCHK(k1_h(c, H_IN, H_T, false, nullptr));
+            QCHK(k2_h(c, H_IN, H_T, H_OUT, false, 0, 0, false, nullptr));
+            QCHK(k1_h(c, H_OUT, H_T, true, nullptr));
+            return k2_h(c, H_OUT, H_T, H_Q, true, 0, 0, false, nullptr);
+          },
+          &ms[2]);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return rc;
+}
+
+int qcd_encode_half(qcd_ctx* c, int n, const void* in_dev, void* codes_dev, float* scale_dev) {
+  QCHK(check_ctx(c));
+  if (n < 0) return fail(QCD_EINVAL, "negative count");
+  if (n == 0) return QCD_OK;
+  if (!in_dev || !codes_dev || !scale_dev) return fail(QCD_EINVAL, "null pointer");
+  HIPCHK(launch_encode_half(n, (const double2*)in_dev, (uint4*)codes_dev, scale_dev, c->stream));
+  return QCD_OK;
+}
+
+int qcd_stream_copy(qcd_ctx* c, void* dst_dev, const void* src_dev, uint64_t n_bytes) {
+  QCHK(check_ctx(c));
+  if (!dst_dev || !src_dev) return fail(QCD_EINVAL, "null pointer");
+  if (n_bytes % 16 != 0 || ((uintptr_t)dst_dev | (uintptr_t)src_dev) % 16 != 0)
+    return fail(QCD_EINVAL, "stream copy needs 16-byte multiples and alignment");
+  HIPCHK(launch_stream_copy((const uint4*)src_dev, (uint4*)dst_dev, n_bytes / 16, c->stream));
+  return QCD_OK;
+}
+
+}  // extern "C"

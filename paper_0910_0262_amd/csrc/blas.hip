@@ -1,0 +1,545 @@
+// Layout conversion, vector updates and reductions for the solver.
+//
+// Packing kernels move caller arrays (site-major complex128) into the
+// per-checkerboard structure-of-arrays fields and back.  The CG kernels keep
+// every scalar of the recurrence on the device (CgState): the finalisation
+// kernels sum the per-workgroup partials in a fixed order (deterministic) and
+// derive alpha, beta and the stopping / reliable-update decisions.
+#include <type_traits>
+
+#include "qcd_internal.h"
+
+namespace qcd {
+
+// ------------------------------------------------------------------ spinor packing
+__global__ void pack_spinor_full_k(Geom g, const double2* __restrict__ user, SpF64 e, SpF64 o) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.V) return;
+  int x[4];
+  lex_coords(i, g, x);
+  const SpF64 f = parity_of(x) ? o : e;
+  const int cb = i >> 1;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) f.p[(size_t)k * f.stride + cb] = user[(size_t)i * 12 + k];
+}
+__global__ void unpack_spinor_full_k(Geom g, SpF64 e, SpF64 o, double2* __restrict__ user) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.V) return;
+  int x[4];
+  lex_coords(i, g, x);
+  const SpF64 f = parity_of(x) ? o : e;
+  const int cb = i >> 1;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) user[(size_t)i * 12 + k] = f.p[(size_t)k * f.stride + cb];
+}
+__global__ void pack_spinor_cb_k(int n, const double2* __restrict__ user, SpF64 f) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) f.p[(size_t)k * f.stride + i] = user[(size_t)i * 12 + k];
+}
+__global__ void unpack_spinor_cb_k(int n, SpF64 f, double2* __restrict__ user) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) user[(size_t)i * 12 + k] = f.p[(size_t)k * f.stride + i];
+}
+
+hipError_t launch_pack_spinor_full(const Geom& g, const double2* user, SpF64 e, SpF64 o, hipStream_t s) {
+  hipLaunchKernelGGL(pack_spinor_full_k, dim3(blocks_for(g.V, 256)), dim3(256), 0, s, g, user, e, o);
+  return hipGetLastError();
+}
+hipError_t launch_unpack_spinor_full(const Geom& g, SpF64 e, SpF64 o, double2* user, hipStream_t s) {
+  hipLaunchKernelGGL(unpack_spinor_full_k, dim3(blocks_for(g.V, 256)), dim3(256), 0, s, g, e, o, user);
+  return hipGetLastError();
+}
+hipError_t launch_pack_spinor_cb(const Geom& g, const double2* user, SpF64 f, hipStream_t s) {
+  hipLaunchKernelGGL(pack_spinor_cb_k, dim3(blocks_for(g.Vh, 256)), dim3(256), 0, s, g.Vh, user, f);
+  return hipGetLastError();
+}
+hipError_t launch_unpack_spinor_cb(const Geom& g, SpF64 f, double2* user, hipStream_t s) {
+  hipLaunchKernelGGL(unpack_spinor_cb_k, dim3(blocks_for(g.Vh, 256)), dim3(256), 0, s, g.Vh, f, user);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ gauge packing
+// user: complex128 [V][4][3][3]; u18: double2 [(mu*2 + par)*9 + k][stride]
+__global__ void pack_gauge_k(Geom g, const double2* __restrict__ user, double2* __restrict__ u18) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 4 * g.V) return;
+  const int i = t >> 2, mu = t & 3;
+  int x[4];
+  lex_coords(i, g, x);
+  const int par = parity_of(x), cb = i >> 1;
+  double2* dst = u18 + (size_t)((mu * 2 + par) * 9) * g.stride + cb;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) dst[(size_t)k * g.stride] = user[(size_t)t * 9 + k];
+}
+__global__ void unpack_gauge_k(Geom g, const double2* __restrict__ u18, double2* __restrict__ user) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 4 * g.V) return;
+  const int i = t >> 2, mu = t & 3;
+  int x[4];
+  lex_coords(i, g, x);
+  const int par = parity_of(x), cb = i >> 1;
+  const double2* src = u18 + (size_t)((mu * 2 + par) * 9) * g.stride + cb;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) user[(size_t)t * 9 + k] = src[(size_t)k * g.stride];
+}
+// FP64 12-real (first two rows) and binary16 12-real copies of the links.
+// binary16 entries are rounded float64 -> float32 -> binary16, both to nearest even.
+__global__ void derive_links_k(Geom g, const double2* __restrict__ u18, double2* __restrict__ u12,
+                               uint2* __restrict__ uh) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 8 * g.Vh) return;
+  const int q = t / g.Vh, cb = t - q * g.Vh;  // q = mu * 2 + par
+  const double2* src = u18 + (size_t)(q * 9) * g.stride + cb;
+  double2 r[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) r[k] = src[(size_t)k * g.stride];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) u12[(size_t)(q * 6 + k) * g.stride + cb] = r[k];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    h4_t h;
+    h[0] = (_Float16)(float)r[2 * k].x;
+    h[1] = (_Float16)(float)r[2 * k].y;
+    h[2] = (_Float16)(float)r[2 * k + 1].x;
+    h[3] = (_Float16)(float)r[2 * k + 1].y;
+    uh[(size_t)(q * 3 + k) * g.stride + cb] = from_h4(h);
+  }
+}
+
+hipError_t launch_pack_gauge(const Geom& g, const double2* user, double2* u18, hipStream_t s) {
+  hipLaunchKernelGGL(pack_gauge_k, dim3(blocks_for(4 * g.V, 256)), dim3(256), 0, s, g, user, u18);
+  return hipGetLastError();
+}
+hipError_t launch_unpack_gauge(const Geom& g, const double2* u18, double2* user, hipStream_t s) {
+  hipLaunchKernelGGL(unpack_gauge_k, dim3(blocks_for(4 * g.V, 256)), dim3(256), 0, s, g, u18, user);
+  return hipGetLastError();
+}
+hipError_t launch_derive_links(const Geom& g, const double2* u18, double2* u12, uint2* uh, hipStream_t s) {
+  hipLaunchKernelGGL(derive_links_k, dim3(blocks_for(8 * g.Vh, 256)), dim3(256), 0, s, g, u18, u12, uh);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ clover packing
+// user [V][36] double2 (= [V][2][36] doubles) <-> clov [(par*36 + k)][stride]
+__global__ void pack_clover_k(Geom g, const double2* __restrict__ user, double2* __restrict__ clov) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.V) return;
+  int x[4];
+  lex_coords(i, g, x);
+  const int par = parity_of(x), cb = i >> 1;
+#pragma unroll 4
+  for (int k = 0; k < 36; ++k) clov[(size_t)(par * 36 + k) * g.stride + cb] = user[(size_t)i * 36 + k];
+}
+__global__ void unpack_clover_full_k(Geom g, const double2* __restrict__ clov, double2* __restrict__ user) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.V) return;
+  int x[4];
+  lex_coords(i, g, x);
+  const int par = parity_of(x), cb = i >> 1;
+#pragma unroll 4
+  for (int k = 0; k < 36; ++k) user[(size_t)i * 36 + k] = clov[(size_t)(par * 36 + k) * g.stride + cb];
+}
+__global__ void unpack_clover_cb_k(Geom g, const double2* __restrict__ clov, double2* __restrict__ user) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.Vh) return;
+#pragma unroll 4
+  for (int k = 0; k < 36; ++k) user[(size_t)i * 36 + k] = clov[(size_t)k * g.stride + i];
+}
+hipError_t launch_pack_clover(const Geom& g, const double2* user, double2* clov, hipStream_t s) {
+  hipLaunchKernelGGL(pack_clover_k, dim3(blocks_for(g.V, 256)), dim3(256), 0, s, g, user, clov);
+  return hipGetLastError();
+}
+hipError_t launch_unpack_clover(const Geom& g, const double2* clov, double2* user, int n_par, int par0,
+                                hipStream_t s) {
+  if (n_par == 2) {
+    hipLaunchKernelGGL(unpack_clover_full_k, dim3(blocks_for(g.V, 256)), dim3(256), 0, s, g, clov, user);
+  } else {
+    hipLaunchKernelGGL(unpack_clover_cb_k, dim3(blocks_for(g.Vh, 256)), dim3(256), 0, s, g,
+                       clov + (size_t)par0 * 36 * g.stride, user);
+  }
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ reductions
+template <class F>
+__global__ void __launch_bounds__(256) norm2_k(Geom g, F x, double* partial) {
+  const int blk = xcd_block(blockIdx.x, gridDim.x);
+  const int i = blk * blockDim.x + threadIdx.x;
+  double n = 0.0;
+  if (i < g.Vh) {
+    Spinor<double> v;
+    load(x, i, v);
+    n = site_norm2(v);
+  }
+  block_sum_store(n, partial, blk);
+}
+__global__ void __launch_bounds__(256) dot_re_k(Geom g, SpF64 a, SpF64 b, double* partial) {
+  const int blk = xcd_block(blockIdx.x, gridDim.x);
+  const int i = blk * blockDim.x + threadIdx.x;
+  double n = 0.0;
+  if (i < g.Vh) {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      const double2 u = a.p[(size_t)k * a.stride + i], v = b.p[(size_t)k * b.stride + i];
+      n += u.x * v.x + u.y * v.y;
+    }
+  }
+  block_sum_store(n, partial, blk);
+}
+hipError_t launch_norm2(const Geom& g, SpRef x, double* partial, int block, hipStream_t s) {
+  const int nb = blocks_for(g.Vh, block);
+  if (x.kind == SP_F64)
+    hipLaunchKernelGGL(norm2_k<SpF64>, dim3(nb), dim3(block), 0, s, g, SpF64{(double2*)x.p, g.stride}, partial);
+  else if (x.kind == SP_F32)
+    hipLaunchKernelGGL(norm2_k<SpF32>, dim3(nb), dim3(block), 0, s, g, SpF32{(float4*)x.p, g.stride}, partial);
+  else if (x.kind == SP_H)
+    hipLaunchKernelGGL(norm2_k<SpH>, dim3(nb), dim3(block), 0, s, g, SpH{(uint4*)x.p, x.s, g.stride}, partial);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+hipError_t launch_dot_re(const Geom& g, SpF64 a, SpF64 b, double* partial, int block, hipStream_t s) {
+  hipLaunchKernelGGL(dot_re_k, dim3(blocks_for(g.Vh, block)), dim3(block), 0, s, g, a, b, partial);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ CG scalar kernels (one workgroup)
+// Each finalisation kernel that ends an iteration posts a copy of the state
+// to mailbox[slot], host-mapped memory the host reads once the iteration's
+// event has completed.
+__device__ __forceinline__ bool finite(double v) { return v == v && v - v == 0.0; }
+
+__device__ __forceinline__ void post(const CgState* st, CgState* mbox, int slot) {
+  if (mbox == nullptr) return;
+  mbox[slot] = *st;
+  __threadfence_system();
+}
+
+__global__ void fin_scalar_k(CgState* st, const double* partial, int n) {
+  const double s = block_sum_partials(partial, n);
+  if (threadIdx.x == 0) st->scalar = s;
+}
+__global__ void fin_init_k(CgState* st, const double* partial, int n, double tol, double delta, int max_iter,
+                           int mixed, CgState* mbox, int slot) {
+  const double rr = block_sum_partials(partial, n);
+  if (threadIdx.x != 0) return;
+  st->rr = rr;
+  st->rr_hi = rr;
+  st->qq = 0.0;
+  st->alpha = 0.0;
+  st->beta = 0.0;
+  st->stop2 = tol * tol * rr;
+  st->maxrr = rr;
+  st->delta2 = delta * delta;
+  st->scalar = rr;
+  st->iter = 0;
+  st->max_iter = max_iter;
+  st->nan = finite(rr) ? 0 : 1;
+  st->done = (st->nan || rr <= st->stop2) ? 1 : 0;
+  st->halt = st->done;
+  st->need_ru = 0;
+  st->do_x = 0;
+  st->do_p = 0;
+  st->mixed = mixed;
+  st->ru_count = 0;
+  post(st, mbox, slot);
+}
+__global__ void fin_alpha_k(CgState* st, const double* partial, int n) {
+  if (st->halt) return;
+  const double qq = block_sum_partials(partial, n);
+  if (threadIdx.x != 0) return;
+  st->qq = qq;
+  if (!(qq > 0.0) || !finite(qq)) {
+    st->nan = 1;
+    st->done = 1;
+    st->halt = 1;
+    st->alpha = 0.0;
+    return;
+  }
+  st->alpha = st->rr / qq;
+}
+// End of an iteration: |r_{k+1}|^2, beta, the stopping test (FP64) or the
+// reliable-update request (mixed; it does not stop the recurrence).
+__global__ void fin_beta_k(CgState* st, const double* partial, int n, CgState* mbox, int slot) {
+  if (st->halt) {
+    if (threadIdx.x == 0) {
+      st->do_x = 0;
+      st->do_p = 0;
+      post(st, mbox, slot);
+    }
+    return;
+  }
+  const double rr_new = block_sum_partials(partial, n);
+  if (threadIdx.x != 0) return;
+  st->iter += 1;
+  if (!finite(rr_new)) {
+    st->nan = 1;
+    st->done = 1;
+    st->halt = 1;
+    st->do_x = 0;
+    st->do_p = 0;
+    post(st, mbox, slot);
+    return;
+  }
+  st->beta = rr_new / st->rr;
+  st->rr = rr_new;
+  st->do_x = 1;
+  if (!st->mixed) {
+    st->done = (rr_new <= st->stop2 || st->iter >= st->max_iter) ? 1 : 0;
+    st->halt = st->done;
+    st->do_p = !st->done;
+  } else {
+    if (rr_new > st->maxrr) st->maxrr = rr_new;
+    if (rr_new <= st->stop2 || rr_new < st->delta2 * st->maxrr || st->iter >= st->max_iter) st->need_ru = 1;
+    st->do_p = 1;
+  }
+  post(st, mbox, slot);
+}
+// After an FP64 residual recomputation r = rhs - A x (partials of |r|^2):
+//   restart = 0 (reliable update): r replaces the recurrence residual, p is kept;
+//   restart = 1 (CG restart): beta = 0, so the following p update sets p = r.
+__global__ void fin_ru_k(CgState* st, const double* partial, int n, int restart, CgState* mbox, int slot) {
+  const double rr = block_sum_partials(partial, n);
+  if (threadIdx.x != 0) return;
+  st->rr_hi = rr;
+  st->ru_count += 1;
+  st->need_ru = 0;
+  st->do_x = 0;
+  if (!finite(rr)) {
+    st->nan = 1;
+    st->done = 1;
+    st->halt = 1;
+    st->do_p = 0;
+    post(st, mbox, slot);
+    return;
+  }
+  if (restart) st->beta = 0.0;
+  st->rr = rr;
+  st->maxrr = rr;
+  st->done = (rr <= st->stop2 || st->iter >= st->max_iter) ? 1 : 0;
+  st->halt = st->done;
+  st->do_p = !st->done;
+  post(st, mbox, slot);
+}
+
+#define FIN_LAUNCH(kernel, ...)                                     \
+  hipLaunchKernelGGL(kernel, dim3(1), dim3(1024), 0, s, __VA_ARGS__); \
+  return hipGetLastError();
+
+hipError_t launch_fin_scalar(CgState* st, const double* partial, int n, hipStream_t s) {
+  FIN_LAUNCH(fin_scalar_k, st, partial, n)
+}
+hipError_t launch_fin_init(CgState* st, const double* partial, int n, double tol, double delta, int max_iter,
+                           int mixed, CgState* mbox, int slot, hipStream_t s) {
+  FIN_LAUNCH(fin_init_k, st, partial, n, tol, delta, max_iter, mixed, mbox, slot)
+}
+hipError_t launch_fin_alpha(CgState* st, const double* partial, int n, hipStream_t s) {
+  FIN_LAUNCH(fin_alpha_k, st, partial, n)
+}
+hipError_t launch_fin_beta(CgState* st, const double* partial, int n, CgState* mbox, int slot, hipStream_t s) {
+  FIN_LAUNCH(fin_beta_k, st, partial, n, mbox, slot)
+}
+hipError_t launch_fin_ru(CgState* st, const double* partial, int n, int restart, CgState* mbox, int slot,
+                         hipStream_t s) {
+  FIN_LAUNCH(fin_ru_k, st, partial, n, restart, mbox, slot)
+}
+
+// ------------------------------------------------------------------ CG vector updates
+// x += alpha p; then p = r + beta p unless the recurrence stopped.
+__global__ void __launch_bounds__(256) xp_update_f64_k(Geom g, const CgState* st, SpF64 x, SpF64 p, SpF64 r) {
+  if (!st->do_x) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.Vh) return;
+  const double al = st->alpha, be = st->beta;
+  const bool dp = st->do_p;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) {
+    const size_t o = (size_t)k * g.stride + i;
+    const double2 pv = p.p[o];
+    double2 xv = x.p[o];
+    xv.x += al * pv.x;
+    xv.y += al * pv.y;
+    x.p[o] = xv;
+    if (dp) {
+      const double2 rv = r.p[o];
+      p.p[o] = make_double2(rv.x + be * pv.x, rv.y + be * pv.y);
+    }
+  }
+}
+__global__ void __launch_bounds__(256) p_restart_f64_k(Geom g, const CgState* st, SpF64 p, SpF64 r) {
+  if (!st->do_p) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.Vh) return;
+  const double be = st->beta;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) {
+    const size_t o = (size_t)k * g.stride + i;
+    const double2 rv = r.p[o];
+    if (be == 0.0) {
+      p.p[o] = rv;
+    } else {
+      const double2 pv = p.p[o];
+      p.p[o] = make_double2(rv.x + be * pv.x, rv.y + be * pv.y);
+    }
+  }
+}
+// mixed: x (FP32) += alpha p (binary16); p = r + beta p, re-encoded.
+__global__ void __launch_bounds__(256) xp_update_h_k(Geom g, const CgState* st, SpF32 x, SpH p, SpH r) {
+  if (!st->do_x) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.Vh) return;
+  const float al = float(st->alpha), be = float(st->beta);
+  Spinor<float> pv, xv;
+  load(p, i, pv);
+  load(x, i, xv);
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) xv.v[s][c] = xv.v[s][c] + al * pv.v[s][c];
+  store(x, i, xv);
+  if (st->do_p) {
+    Spinor<float> rv;
+    load(r, i, rv);
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) rv.v[s][c] = rv.v[s][c] + be * pv.v[s][c];
+    store(p, i, rv);
+  }
+}
+// x_hi += x_lo; x_lo = 0
+__global__ void __launch_bounds__(256) ru_accum_k(Geom g, SpF64 xhi, SpF32 xlo) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.Vh) return;
+  Spinor<double> a, b;
+  load(xhi, i, a);
+  load(xlo, i, b);
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) a.v[s][c] = a.v[s][c] + b.v[s][c];
+  store(xhi, i, a);
+  Spinor<float> z;
+  zero(z);
+  store(xlo, i, z);
+}
+
+hipError_t launch_xp_update_f64(const Geom& g, const CgState* st, SpF64 x, SpF64 p, SpF64 r, int block,
+                                hipStream_t s) {
+  hipLaunchKernelGGL(xp_update_f64_k, dim3(blocks_for(g.Vh, block)), dim3(block), 0, s, g, st, x, p, r);
+  return hipGetLastError();
+}
+hipError_t launch_p_restart_f64(const Geom& g, const CgState* st, SpF64 p, SpF64 r, int block, hipStream_t s) {
+  hipLaunchKernelGGL(p_restart_f64_k, dim3(blocks_for(g.Vh, block)), dim3(block), 0, s, g, st, p, r);
+  return hipGetLastError();
+}
+hipError_t launch_xp_update_h(const Geom& g, const CgState* st, SpF32 x, SpH p, SpH r, int block, hipStream_t s) {
+  hipLaunchKernelGGL(xp_update_h_k, dim3(blocks_for(g.Vh, block)), dim3(block), 0, s, g, st, x, p, r);
+  return hipGetLastError();
+}
+hipError_t launch_ru_accum(const Geom& g, SpF64 xhi, SpF32 xlo, int block, hipStream_t s) {
+  hipLaunchKernelGGL(ru_accum_k, dim3(blocks_for(g.Vh, block)), dim3(block), 0, s, g, xhi, xlo);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ conversions
+template <class FS, class FD>
+__global__ void __launch_bounds__(256) convert_k(Geom g, FS src, FD dst) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.Vh) return;
+  Spinor<double> vd;
+  load(src, i, vd);
+  if constexpr (std::is_same_v<FD, SpF64>) {
+    store(dst, i, vd);
+  } else {
+    // round to float32 first: the binary16 and FP32 encoders work on float32 values
+    Spinor<float> vf;
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) vf.v[s][c] = {float(vd.v[s][c].re), float(vd.v[s][c].im)};
+    store(dst, i, vf);
+  }
+}
+template <class FS>
+static hipError_t convert_to(const Geom& g, FS src, SpRef dst, int block, hipStream_t s) {
+  const int nb = blocks_for(g.Vh, block);
+  if (dst.kind == SP_F64)
+    hipLaunchKernelGGL((convert_k<FS, SpF64>), dim3(nb), dim3(block), 0, s, g, src, SpF64{(double2*)dst.p, g.stride});
+  else if (dst.kind == SP_F32)
+    hipLaunchKernelGGL((convert_k<FS, SpF32>), dim3(nb), dim3(block), 0, s, g, src, SpF32{(float4*)dst.p, g.stride});
+  else if (dst.kind == SP_H)
+    hipLaunchKernelGGL((convert_k<FS, SpH>), dim3(nb), dim3(block), 0, s, g, src, SpH{(uint4*)dst.p, dst.s, g.stride});
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+hipError_t launch_convert(const Geom& g, SpRef src, SpRef dst, int block, hipStream_t s) {
+  if (src.kind == SP_F64) return convert_to(g, SpF64{(double2*)src.p, g.stride}, dst, block, s);
+  if (src.kind == SP_F32) return convert_to(g, SpF32{(float4*)src.p, g.stride}, dst, block, s);
+  if (src.kind == SP_H) return convert_to(g, SpH{(uint4*)src.p, src.s, g.stride}, dst, block, s);
+  return hipErrorInvalidValue;
+}
+
+template <class F>
+__global__ void __launch_bounds__(256) zero_k(Geom g, F x) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.Vh) return;
+  Spinor<float> z;
+  zero(z);
+  store(x, i, z);
+}
+hipError_t launch_zero(const Geom& g, SpRef x, int block, hipStream_t s) {
+  const int nb = blocks_for(g.Vh, block);
+  if (x.kind == SP_F64)
+    hipLaunchKernelGGL(zero_k<SpF64>, dim3(nb), dim3(block), 0, s, g, SpF64{(double2*)x.p, g.stride});
+  else if (x.kind == SP_F32)
+    hipLaunchKernelGGL(zero_k<SpF32>, dim3(nb), dim3(block), 0, s, g, SpF32{(float4*)x.p, g.stride});
+  else if (x.kind == SP_H)
+    hipLaunchKernelGGL(zero_k<SpH>, dim3(nb), dim3(block), 0, s, g, SpH{(uint4*)x.p, x.s, g.stride});
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+// Reference encoder for checking: user complex128 [n][12] -> codes [n][3] x 8 binary16, scale [n]
+__global__ void encode_half_k(int n, const double2* __restrict__ user, uint4* __restrict__ codes,
+                              float* __restrict__ scale) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  Spinor<float> v;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) {
+    const double2 d = user[(size_t)i * 12 + k];
+    v.v[k / 3][k % 3] = {float(d.x), float(d.y)};
+  }
+  h8_t h[3];
+  const float m = encode_site(v, h);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) codes[(size_t)i * 3 + k] = from_h8(h[k]);
+  scale[i] = m;
+}
+hipError_t launch_encode_half(int n, const double2* user, uint4* codes, float* scale, hipStream_t s) {
+  hipLaunchKernelGGL(encode_half_k, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, user, codes, scale);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ bandwidth calibration
+__global__ void __launch_bounds__(256) stream_copy_k(const uint4* __restrict__ src, uint4* __restrict__ dst,
+                                                     uint64_t n) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
+}
+hipError_t launch_stream_copy(const uint4* src, uint4* dst, uint64_t n16, hipStream_t s) {
+  uint64_t nb = (n16 + 255) / 256;
+  if (nb > 256 * 64) nb = 256 * 64;
+  if (nb == 0) return hipSuccess;
+  hipLaunchKernelGGL(stream_copy_k, dim3((unsigned)nb), dim3(256), 0, s, src, dst, n16);
+  return hipGetLastError();
+}
+
+}  // namespace qcd

@@ -1,0 +1,260 @@
+// Clover term: field strength from the four-leaf clover and the two 6x6
+// Hermitian blocks of A = 1 - kappa c_sw sum_{mu<nu} sigma_mu,nu (x) F_mu,nu,
+// then the inverse of the odd-site blocks for the even-odd preconditioner.
+//
+// In the chiral basis sigma_mu,nu = diag(B_up, B_dn) with 2x2 blocks
+//   (0,1): -s3, -s3   (0,2): s2, s2   (0,3): s1, -s1
+//   (1,2): -s1, -s1   (1,3): s2, -s2  (2,3): s3, -s3
+// so sum sigma (x) F = s1 (x) X + s2 (x) Y + s3 (x) Z per chirality with
+//   upper: X = F03 - F12, Y = F02 + F13, Z = F23 - F01
+//   lower: X = -F12 - F03, Y = F02 - F13, Z = -F01 - F23,
+// and s1 (x) X + s2 (x) Y + s3 (x) Z = [[Z, X - iY], [X + iY, -Z]].
+#include "qcd_internal.h"
+
+namespace qcd {
+
+__device__ __forceinline__ Mat<double> link_at(const double2* u18, const Geom& g, int mu, const int x[4]) {
+  Mat<double> u;
+  load_link(LinkF64<9>{u18, g.stride}, mu, parity_of(x), lex(x, g) >> 1, u);
+  return u;
+}
+__device__ __forceinline__ void shift(const Geom& g, const int x[4], int mu, int n, int y[4]) {
+  y[0] = x[0];
+  y[1] = x[1];
+  y[2] = x[2];
+  y[3] = x[3];
+  y[mu] = (x[mu] + n + 2 * g.X[mu]) % g.X[mu];
+}
+
+// F_mu,nu(x) = traceless part of (Q - Q^dag) / (8i), Q the sum of the four
+// counter-clockwise leaves in the mu-nu plane starting at x.
+__device__ Mat<double> field_strength(const double2* u18, const Geom& g, const int x[4], int mu, int nu) {
+  int xp_mu[4], xp_nu[4], xm_mu[4], xm_nu[4], xm_mu_p_nu[4], xm_mu_m_nu[4], xp_mu_m_nu[4];
+  shift(g, x, mu, 1, xp_mu);
+  shift(g, x, nu, 1, xp_nu);
+  shift(g, x, mu, -1, xm_mu);
+  shift(g, x, nu, -1, xm_nu);
+  shift(g, xm_mu, nu, 1, xm_mu_p_nu);
+  shift(g, xm_mu, nu, -1, xm_mu_m_nu);
+  shift(g, xp_mu, nu, -1, xp_mu_m_nu);
+
+  const Mat<double> um_x = link_at(u18, g, mu, x), un_x = link_at(u18, g, nu, x);
+  Mat<double> q;
+  // U_mu(x) U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag
+  q = mm(mm(um_x, link_at(u18, g, nu, xp_mu)), mm(adj(link_at(u18, g, mu, xp_nu)), adj(un_x)));
+  // U_nu(x) U_mu(x-mu+nu)^dag U_nu(x-mu)^dag U_mu(x-mu)
+  const Mat<double> um_xm = link_at(u18, g, mu, xm_mu);
+  q = madd(q, mm(mm(un_x, adj(link_at(u18, g, mu, xm_mu_p_nu))), mm(adj(link_at(u18, g, nu, xm_mu)), um_xm)));
+  // U_mu(x-mu)^dag U_nu(x-mu-nu)^dag U_mu(x-mu-nu) U_nu(x-nu)
+  const Mat<double> un_xm = link_at(u18, g, nu, xm_nu);
+  q = madd(q, mm(mm(adj(um_xm), adj(link_at(u18, g, nu, xm_mu_m_nu))), mm(link_at(u18, g, mu, xm_mu_m_nu), un_xm)));
+  // U_nu(x-nu)^dag U_mu(x-nu) U_nu(x+mu-nu) U_mu(x)^dag
+  q = madd(q, mm(mm(adj(un_xm), link_at(u18, g, mu, xm_nu)), mm(link_at(u18, g, nu, xp_mu_m_nu), adj(um_x))));
+
+  Mat<double> f;
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      const Cx<double> d = q.m[a][b] - conj(q.m[b][a]);
+      f.m[a][b] = {d.im / 8.0, -d.re / 8.0};  // d / (8 i)
+    }
+  const double tr = (f.m[0][0].re + f.m[1][1].re + f.m[2][2].re) / 3.0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) f.m[a][a].re -= tr;
+  return f;
+}
+
+__global__ void __launch_bounds__(64) clover_build_k(Geom g, const double2* __restrict__ u18, double kc,
+                                                     double2* __restrict__ clov) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.V) return;
+  int x[4];
+  lex_coords(i, g, x);
+  const int par = parity_of(x), cb = i >> 1;
+  const Mat<double> f01 = field_strength(u18, g, x, 0, 1);
+  const Mat<double> f02 = field_strength(u18, g, x, 0, 2);
+  const Mat<double> f03 = field_strength(u18, g, x, 0, 3);
+  const Mat<double> f12 = field_strength(u18, g, x, 1, 2);
+  const Mat<double> f13 = field_strength(u18, g, x, 1, 3);
+  const Mat<double> f23 = field_strength(u18, g, x, 2, 3);
+#pragma unroll 1
+  for (int b = 0; b < 2; ++b) {
+    Mat<double> X, Y, Z;
+    if (b == 0) {
+      X = msub(f03, f12);
+      Y = madd(f02, f13);
+      Z = msub(f23, f01);
+    } else {
+      X = msub(mzero<double>(), madd(f12, f03));
+      Y = msub(f02, f13);
+      Z = msub(mzero<double>(), madd(f01, f23));
+    }
+    // 6x6 block entry (r, c): sub-block (r / 3, c / 3), colour (r % 3, c % 3)
+    Cx<double> blk[6][6];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const Cx<double> z = Z.m[a][c], xx = X.m[a][c], yy = Y.m[a][c];
+        const Cx<double> one = {a == c ? 1.0 : 0.0, 0.0};
+        blk[a][c] = one - kc * z;
+        blk[3 + a][3 + c] = one + kc * z;
+        blk[a][3 + c] = -kc * (xx - ti(yy));
+        blk[3 + a][c] = -kc * (xx + ti(yy));
+      }
+    double2* dst = clov + (size_t)(par * 36 + b * 18) * g.stride + cb;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) dst[(size_t)k * g.stride] = make_double2(blk[2 * k][2 * k].re, blk[2 * k + 1][2 * k + 1].re);
+#pragma unroll
+    for (int r = 0; r < 6; ++r)
+#pragma unroll
+      for (int c = r + 1; c < 6; ++c)
+        dst[(size_t)(3 + offd(r, c)) * g.stride] = make_double2(blk[r][c].re, blk[r][c].im);
+  }
+}
+
+hipError_t launch_clover_build(const Geom& g, const double2* u18, double kappa, double csw, double2* clov,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(clover_build_k, dim3(blocks_for(g.V, 64)), dim3(64), 0, s, g, u18, kappa * csw, clov);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ inversion
+// Hermitian positive-definite 6x6 inverse by Cholesky A = L L^dag:
+// A^{-1} = L^{-dag} L^{-1}.  Returns false if a pivot is not positive.
+__device__ bool invert_block(const Block<double>& a, Block<double>& inv) {
+  Cx<double> L[6][6];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    double d = a.d[j];
+#pragma unroll
+    for (int k = 0; k < j; ++k) d -= norm2(L[j][k]);
+    if (!(d > 0.0)) return false;
+    const double ljj = sqrt(d), rinv = 1.0 / ljj;
+    L[j][j] = {ljj, 0.0};
+#pragma unroll
+    for (int i = j + 1; i < 6; ++i) {
+      Cx<double> s = conj(a.o[offd(j, i)]);  // A_ij for i > j
+#pragma unroll
+      for (int k = 0; k < j; ++k) s = s - L[i][k] * conj(L[j][k]);
+      L[i][j] = rinv * s;
+    }
+  }
+  // T = L^{-1}, lower triangular
+  Cx<double> T[6][6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    T[i][i] = {1.0 / L[i][i].re, 0.0};
+#pragma unroll
+    for (int j = 0; j < i; ++j) {
+      Cx<double> s = {0.0, 0.0};
+#pragma unroll
+      for (int k = j; k < i; ++k) s = s + L[i][k] * T[k][j];
+      T[i][j] = (-1.0 / L[i][i].re) * s;
+    }
+  }
+  // inv = T^dag T: inv_rc = sum_{k >= max(r,c)} conj(T_kr) T_kc
+#pragma unroll
+  for (int r = 0; r < 6; ++r) {
+    double d = 0.0;
+#pragma unroll
+    for (int k = r; k < 6; ++k) d += norm2(T[k][r]);
+    inv.d[r] = d;
+#pragma unroll
+    for (int c = r + 1; c < 6; ++c) {
+      Cx<double> s = {0.0, 0.0};
+#pragma unroll
+      for (int k = c; k < 6; ++k) s = s + cmulc(T[k][r], T[k][c]);
+      inv.o[offd(r, c)] = s;
+    }
+  }
+  return true;
+}
+
+__device__ void store_block_f64(double2* base, int stride, int i, const Block<double>& b) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k) base[(size_t)k * stride + i] = make_double2(b.d[2 * k], b.d[2 * k + 1]);
+#pragma unroll
+  for (int k = 0; k < 15; ++k) base[(size_t)(3 + k) * stride + i] = make_double2(b.o[k].re, b.o[k].im);
+}
+__device__ void block_reals(const Block<double>& b, double r[36]) {
+#pragma unroll
+  for (int k = 0; k < 6; ++k) r[k] = b.d[k];
+#pragma unroll
+  for (int k = 0; k < 15; ++k) {
+    r[6 + 2 * k] = b.o[k].re;
+    r[7 + 2 * k] = b.o[k].im;
+  }
+}
+// FP32 copy: 18 float4 chunks, reals [b * 36 + r]; binary16 copy: 9 chunks of
+// 8 halves with a per-block float32 scale (max |real|).
+__device__ void store_site_low(const Block<double> blk[2], float4* f32, uint4* h16, float2* hs, int stride, int i) {
+  float r[72];
+  float sc[2];
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    double rr[36];
+    block_reals(blk[b], rr);
+    float m = 0.f;
+#pragma unroll
+    for (int k = 0; k < 36; ++k) {
+      r[36 * b + k] = float(rr[k]);
+      m = fmaxf(m, fabsf(r[36 * b + k]));
+    }
+    sc[b] = m;
+  }
+#pragma unroll
+  for (int k = 0; k < 18; ++k) f32[(size_t)k * stride + i] = make_float4(r[4 * k], r[4 * k + 1], r[4 * k + 2], r[4 * k + 3]);
+  const float inv0 = sc[0] > 0.f ? 1.0f / sc[0] : 0.f, inv1 = sc[1] > 0.f ? 1.0f / sc[1] : 0.f;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    h8_t h;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int q = 8 * k + j;
+      h[j] = (_Float16)(r[q] * (q < 36 ? inv0 : inv1));
+    }
+    h16[(size_t)k * stride + i] = from_h8(h);
+  }
+  hs[i] = make_float2(sc[0], sc[1]);
+}
+
+__global__ void __launch_bounds__(64) clover_invert_k(Geom g, const double2* __restrict__ clov,
+                                                      double2* __restrict__ clov_inv, float4* clov32_e,
+                                                      float4* clovinv32_o, uint4* clovh_e, float2* clovh_es,
+                                                      uint4* clovinvh_o, float2* clovinvh_os, int* status) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.Vh) return;
+  const CloverF64 ce{clov, g.stride}, co{clov + (size_t)36 * g.stride, g.stride};
+  Block<double> a[2], inv[2];
+  // even sites: low-precision copies of A_ee
+  load_block(ce, i, 0, a[0]);
+  load_block(ce, i, 1, a[1]);
+  store_site_low(a, clov32_e, clovh_e, clovh_es, g.stride, i);
+  // odd sites: A_oo^{-1}
+  load_block(co, i, 0, a[0]);
+  load_block(co, i, 1, a[1]);
+  bool ok = true;
+#pragma unroll 1
+  for (int b = 0; b < 2; ++b) {
+    if (!invert_block(a[b], inv[b])) {
+      ok = false;
+      for (int k = 0; k < 6; ++k) inv[b].d[k] = 0.0;
+      for (int k = 0; k < 15; ++k) inv[b].o[k] = {0.0, 0.0};
+    }
+    store_block_f64(clov_inv + (size_t)(b * 18) * g.stride, g.stride, i, inv[b]);
+  }
+  store_site_low(inv, clovinv32_o, clovinvh_o, clovinvh_os, g.stride, i);
+  if (!ok) *status = 1;
+}
+
+hipError_t launch_clover_invert(const Geom& g, const double2* clov, double2* clov_inv, float4* clov32_e,
+                                float4* clovinv32_o, uint4* clovh_e, float2* clovh_es, uint4* clovinvh_o,
+                                float2* clovinvh_os, int* status, hipStream_t s) {
+  hipLaunchKernelGGL(clover_invert_k, dim3(blocks_for(g.Vh, 64)), dim3(64), 0, s, g, clov, clov_inv, clov32_e,
+                     clovinv32_o, clovh_e, clovh_es, clovinvh_o, clovinvh_os, status);
+  return hipGetLastError();
+}
+
+}  // namespace qcd

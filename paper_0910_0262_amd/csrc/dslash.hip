@@ -1,0 +1,244 @@
+// Wilson-clover hopping kernels for gfx950.
+//
+// One work-item per output site of one checkerboard.  For every direction
+// the two neighbour spinors (opposite checkerboard) are spin-projected to
+// half spinors, multiplied by the link (or its adjoint), rebuilt and
+// accumulated; the 6x6 clover blocks are applied before (site term) or
+// after (A^{-1} of the even-odd preconditioner) the hop; an epilogue stores
+// the result, or fuses the CG residual update, and leaves per-workgroup
+// partial sums of |out|^2 for a deterministic two-pass reduction.
+//
+// The same template serves every form the solver needs:
+//   k1:  t_o = A_oo^{-1} H_oe psi_e                  (site none, post clover)
+//   k2:  out_e = A_ee psi_e - kappa^2 H_eo t_o       (site with clover)
+//   M:   out_p = A_pp psi_p - kappa H psi_(1-p)      (site with clover)
+//   bhat = b_e + kappa H_eo u_o, x_o = A^{-1}(b_o + kappa H_oe x_e)
+// Mhat^dag = g5 Mhat g5 uses the g5in / g5out switches.
+#include "qcd_internal.h"
+
+namespace qcd {
+
+struct SpNone {};
+
+template <class SIn, class SSite, class SOut, class LK, class CPre, class CPost>
+struct DArgs {
+  Geom g;
+  int par_out;
+  SIn in;
+  SSite site;
+  SOut out;
+  SOut y;
+  LK U;
+  CPre cpre;
+  CPost cpost;
+  double c;
+  int epi;
+  double a;
+  int a_from_state;
+  int g5in, g5out;
+  const CgState* st;
+  double* partial;
+};
+
+template <int MU, typename R, class A>
+__device__ __forceinline__ void hop_dir(const A& a, int i, const int x[4], Spinor<R>& acc) {
+  const Geom& g = a.g;
+  int y[4] = {x[0], x[1], x[2], x[3]};
+  y[MU] = (x[MU] + 1 == g.X[MU]) ? 0 : x[MU] + 1;
+  const int nf = lex(y, g) >> 1;
+  y[MU] = (x[MU] == 0 ? g.X[MU] : x[MU]) - 1;
+  const int nb = lex(y, g) >> 1;
+
+  Spinor<R> pf, pb;
+  Mat<R> uf, ub;
+  load(a.in, nf, pf);
+  load_link(a.U, MU, a.par_out, i, uf);
+  load(a.in, nb, pb);
+  load_link(a.U, MU, 1 - a.par_out, nb, ub);
+  if (a.g5in) {
+    neg_lower(pf);
+    neg_lower(pb);
+  }
+  Half<R> h, uh;
+  // forward: (1 - gamma_mu) U_mu(x) psi(x + mu)
+  project<MU, -1>(pf, h);
+  mul_mat(uf, h, uh);
+  if (MU == 3 && g.tb < 0 && x[3] == g.X[3] - 1) {
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) uh.h[k][c] = -uh.h[k][c];
+  }
+  accumulate<MU, -1>(acc, uh);
+  // backward: (1 + gamma_mu) U_mu(x - mu)^dag psi(x - mu)
+  project<MU, +1>(pb, h);
+  mul_adj(ub, h, uh);
+  if (MU == 3 && g.tb < 0 && x[3] == 0) {
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) uh.h[k][c] = -uh.h[k][c];
+  }
+  accumulate<MU, +1>(acc, uh);
+}
+
+template <typename R, int SITE, bool POST, class A>
+__global__ void __launch_bounds__(256) dslash_kernel(A a) {
+  if (a.st != nullptr && a.st->halt) return;  // uniform over the grid
+  const int blk = xcd_block(blockIdx.x, gridDim.x);
+  const int i = blk * blockDim.x + threadIdx.x;
+  double nrm = 0.0;
+  if (i < a.g.Vh) {
+    int x[4];
+    cb_coords(i, a.par_out, a.g, x);
+    Spinor<R> acc;
+    zero(acc);
+    hop_dir<0>(a, i, x, acc);
+    hop_dir<1>(a, i, x, acc);
+    hop_dir<2>(a, i, x, acc);
+    hop_dir<3>(a, i, x, acc);
+    if (a.g5out) neg_lower(acc);
+    const R c = R(a.c);
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) acc.v[s][k] = c * acc.v[s][k];
+    if constexpr (SITE != 0) {
+      Spinor<R> sv;
+      load(a.site, i, sv);
+      if constexpr (SITE == 2) apply_clover(a.cpre, i, sv);
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) acc.v[s][k] = acc.v[s][k] + sv.v[s][k];
+    }
+    if constexpr (POST) apply_clover(a.cpost, i, acc);
+    if (a.epi == 2) {
+      Spinor<R> yv;
+      load(a.y, i, yv);
+      const R al = a.a_from_state ? R(-a.st->alpha) : R(a.a);
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) yv.v[s][k] = yv.v[s][k] + al * acc.v[s][k];
+      store(a.out, i, yv);
+      nrm = site_norm2(yv);
+    } else {
+      store(a.out, i, acc);
+      if (a.epi == 1) nrm = site_norm2(acc);
+    }
+  }
+  if (a.epi >= 1) block_sum_store(nrm, a.partial, blk);
+}
+
+// ------------------------------------------------------------------ dispatch
+template <class T>
+T sp_of(const SpRef& r, int stride);
+template <>
+SpF64 sp_of<SpF64>(const SpRef& r, int stride) { return SpF64{(double2*)r.p, stride}; }
+template <>
+SpF32 sp_of<SpF32>(const SpRef& r, int stride) { return SpF32{(float4*)r.p, stride}; }
+template <>
+SpH sp_of<SpH>(const SpRef& r, int stride) { return SpH{(uint4*)r.p, r.s, stride}; }
+template <>
+SpNone sp_of<SpNone>(const SpRef&, int) { return SpNone{}; }
+
+template <class T>
+T cl_of(const ClovRef& r, int stride);
+template <>
+CloverF64 cl_of<CloverF64>(const ClovRef& r, int stride) { return CloverF64{(const double2*)r.p, stride}; }
+template <>
+CloverF32 cl_of<CloverF32>(const ClovRef& r, int stride) { return CloverF32{(const float4*)r.p, stride}; }
+template <>
+CloverH cl_of<CloverH>(const ClovRef& r, int stride) { return CloverH{(const uint4*)r.p, r.s, stride}; }
+template <>
+CloverNone cl_of<CloverNone>(const ClovRef&, int) { return CloverNone{}; }
+
+template <class T>
+T lk_of(const void* p, int stride);
+template <>
+LinkF64<9> lk_of<LinkF64<9>>(const void* p, int stride) { return LinkF64<9>{(const double2*)p, stride}; }
+template <>
+LinkF64<6> lk_of<LinkF64<6>>(const void* p, int stride) { return LinkF64<6>{(const double2*)p, stride}; }
+template <>
+LinkH12 lk_of<LinkH12>(const void* p, int stride) { return LinkH12{(const uint2*)p, stride}; }
+
+template <typename R, class SIn, class SSite, class SOut, class LK, class CPre, class CPost, int SITE, bool POST>
+static hipError_t run(const Geom& g, const DslashOp& op, int block, hipStream_t s) {
+  DArgs<SIn, SSite, SOut, LK, CPre, CPost> a;
+  a.g = g;
+  a.par_out = op.par_out;
+  a.in = sp_of<SIn>(op.in, g.stride);
+  a.site = sp_of<SSite>(op.site, g.stride);
+  a.out = sp_of<SOut>(op.out, g.stride);
+  a.y = op.epi == 2 ? sp_of<SOut>(op.y, g.stride) : a.out;
+  a.U = lk_of<LK>(op.links, g.stride);
+  a.cpre = cl_of<CPre>(op.cpre, g.stride);
+  a.cpost = cl_of<CPost>(op.cpost, g.stride);
+  a.c = op.c;
+  a.epi = op.epi;
+  a.a = op.a;
+  a.a_from_state = op.a_from_state;
+  a.g5in = op.g5in;
+  a.g5out = op.g5out;
+  a.st = op.st;
+  a.partial = op.partial;
+  const int nb = blocks_for(g.Vh, block);
+  hipLaunchKernelGGL((dslash_kernel<R, SITE, POST, decltype(a)>), dim3(nb), dim3(block), 0, s, a);
+  return hipGetLastError();
+}
+
+template <int NC>
+static hipError_t run_f64(const Geom& g, const DslashOp& op, int block, hipStream_t s) {
+  using L = LinkF64<NC>;
+  if (op.site_mode == 0 && op.post)
+    return run<double, SpF64, SpNone, SpF64, L, CloverNone, CloverF64, 0, true>(g, op, block, s);
+  if (op.site_mode == 2 && !op.post)
+    return run<double, SpF64, SpF64, SpF64, L, CloverF64, CloverNone, 2, false>(g, op, block, s);
+  if (op.site_mode == 1 && !op.post)
+    return run<double, SpF64, SpF64, SpF64, L, CloverNone, CloverNone, 1, false>(g, op, block, s);
+  if (op.site_mode == 1 && op.post)
+    return run<double, SpF64, SpF64, SpF64, L, CloverNone, CloverF64, 1, true>(g, op, block, s);
+  return hipErrorInvalidValue;
+}
+
+template <class CL>
+static hipError_t run_mixed(const Geom& g, const DslashOp& op, int block, hipStream_t s) {
+  if (op.site_mode == 0 && op.post)
+    return run<float, SpH, SpNone, SpH, LinkH12, CloverNone, CL, 0, true>(g, op, block, s);
+  if (op.site_mode == 2 && !op.post)
+    return run<float, SpH, SpH, SpH, LinkH12, CL, CloverNone, 2, false>(g, op, block, s);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_dslash(const Geom& g, const DslashOp& op, int block, hipStream_t s) {
+  if (op.in.kind == SP_F64) {
+    if (op.link_kind == LK_F64_12) return run_f64<6>(g, op, block, s);
+    if (op.link_kind == LK_F64_18) return run_f64<9>(g, op, block, s);
+    return hipErrorInvalidValue;
+  }
+  if (op.in.kind == SP_H && op.link_kind == LK_H12) {
+    const int ck = op.post ? op.cpost.kind : op.cpre.kind;
+    if (ck == CL_F32) return run_mixed<CloverF32>(g, op, block, s);
+    if (ck == CL_H) return run_mixed<CloverH>(g, op, block, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+// ------------------------------------------------------------------ clover only
+__global__ void __launch_bounds__(256) clover_apply_kernel(Geom g, SpF64 in, SpF64 out, CloverF64 c) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.Vh) return;
+  Spinor<double> v;
+  load(in, i, v);
+  apply_clover(c, i, v);
+  store(out, i, v);
+}
+
+hipError_t launch_clover_apply(const Geom& g, SpF64 in, SpF64 out, const double2* clov, hipStream_t s) {
+  hipLaunchKernelGGL(clover_apply_kernel, dim3(blocks_for(g.Vh, 256)), dim3(256), 0, s, g, in, out,
+                     CloverF64{clov, g.stride});
+  return hipGetLastError();
+}
+
+}  // namespace qcd

@@ -1,0 +1,397 @@
+// Fermion force for S = phi^dag (Mhat^dag Mhat)^{-1} phi and the HMD link and
+// momentum updates.
+//
+// With X = (Mhat^dag Mhat)^{-1} phi, Y = Mhat X, Z = A_oo^{-1} H_oe X and
+// W = A_oo^{-1} H_eo^dag Y, the first-order change of S is
+//   dS = 2 kappa^2 Re[l^dag dH r] + 2 kappa c_sw Re sum_x,mu<nu tr[dF_mu,nu(x) Gamma_mu,nu(x)]
+// with full-lattice l = (Y even, W odd), r = (X even, Z odd) and
+// Gamma_mu,nu(x)_ba = sum_s,s' (sigma_mu,nu)_ss' Lambda(x)_(s'b),(sa),
+// Lambda = X Y^dag on even sites and kappa^2 Z W^dag on odd sites.
+// The kernels write G = dS/dRe U + i dS/dIm U per link (dS = Re sum conj(G) dU).
+//
+// Hopping part, per link U_mu(x) (eta = boundary sign of the hop):
+//   G = 2 kappa^2 eta (B^dag + C),
+//   B = sum_k h-_k(r(x+mu)) h-_k(l(x))^dag,  C = sum_k h+_k(r(x)) h+_k(l(x+mu))^dag,
+// where h-(v), h+(v) are the upper spin pair of (1 -+ gamma_mu) v: the
+// projectors are rank two, so the spin trace reduces to two colour outer products.
+//
+// Clover part: Re tr[dF Gamma] = (1/4) Im tr[dQ Xi] with Xi the Hermitian part
+// of the traceless part of Gamma; each link enters the leaves of 6 plaquettes
+// at 4 corners each, and a leaf derivative is the product of the other three
+// links with Xi inserted at the leaf's corner.
+#include "qcd_internal.h"
+
+namespace qcd {
+
+// ------------------------------------------------------------------ helpers
+__device__ __forceinline__ void shift4(const Geom& g, const int x[4], int mu, int n, int y[4]) {
+  y[0] = x[0];
+  y[1] = x[1];
+  y[2] = x[2];
+  y[3] = x[3];
+  y[mu] = (x[mu] + n + 2 * g.X[mu]) % g.X[mu];
+}
+__device__ __forceinline__ Mat<double> u_at(const double2* u18, const Geom& g, int mu, const int x[4]) {
+  Mat<double> u;
+  load_link(LinkF64<9>{u18, g.stride}, mu, parity_of(x), lex(x, g) >> 1, u);
+  return u;
+}
+__device__ __forceinline__ void spinor_at(SpF64 e, SpF64 o, const Geom& g, const int x[4], Spinor<double>& v) {
+  load(parity_of(x) ? o : e, lex(x, g) >> 1, v);
+}
+// out += sum_k a_k (x) b_k^dag  (colour outer products, out[row][col] = a_row conj(b_col))
+__device__ __forceinline__ void outer_acc(Mat<double>& out, const Half<double>& a, const Half<double>& b) {
+#pragma unroll
+  for (int k = 0; k < 2; ++k)
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) out.m[r][c] = out.m[r][c] + a.h[k][r] * conj(b.h[k][c]);
+}
+__device__ __forceinline__ void store_mat(double2* base, int stride, int i, const Mat<double>& m) {
+#pragma unroll
+  for (int k = 0; k < 9; ++k) base[(size_t)k * stride + i] = make_double2(m.m[k / 3][k % 3].re, m.m[k / 3][k % 3].im);
+}
+__device__ __forceinline__ Mat<double> load_mat(const double2* base, int stride, int i) {
+  Mat<double> m;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    const double2 d = base[(size_t)k * stride + i];
+    m.m[k / 3][k % 3] = {d.x, d.y};
+  }
+  return m;
+}
+
+// ------------------------------------------------------------------ hopping force
+template <int MU>
+__device__ __forceinline__ Mat<double> hop_force_dir(const Geom& g, const int x[4], SpF64 le, SpF64 lo, SpF64 re,
+                                                     SpF64 ro) {
+  int y[4];
+  shift4(g, x, MU, 1, y);
+  Spinor<double> l_x, r_x, l_y, r_y;
+  spinor_at(le, lo, g, x, l_x);
+  spinor_at(re, ro, g, x, r_x);
+  spinor_at(le, lo, g, y, l_y);
+  spinor_at(re, ro, g, y, r_y);
+  Half<double> a, b;
+  Mat<double> B = mzero<double>(), C = mzero<double>();
+  project<MU, -1>(r_y, a);
+  project<MU, -1>(l_x, b);
+  outer_acc(B, a, b);
+  project<MU, +1>(r_x, a);
+  project<MU, +1>(l_y, b);
+  outer_acc(C, a, b);
+  return madd(adj(B), C);
+}
+
+__global__ void __launch_bounds__(128) force_hop_k(Geom g, const double2* __restrict__ u18, SpF64 le, SpF64 lo,
+                                                   SpF64 re, SpF64 ro, double coef, double2* __restrict__ gint) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.V) return;
+  int x[4];
+  lex_coords(i, g, x);
+  const int par = parity_of(x), cb = i >> 1;
+  Mat<double> f[4];
+  f[0] = hop_force_dir<0>(g, x, le, lo, re, ro);
+  f[1] = hop_force_dir<1>(g, x, le, lo, re, ro);
+  f[2] = hop_force_dir<2>(g, x, le, lo, re, ro);
+  f[3] = hop_force_dir<3>(g, x, le, lo, re, ro);
+#pragma unroll
+  for (int mu = 0; mu < 4; ++mu) {
+    const double eta = (mu == 3 && g.tb < 0 && x[3] == g.X[3] - 1) ? -coef : coef;
+    Mat<double> m;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) m.m[k / 3][k % 3] = eta * f[mu].m[k / 3][k % 3];
+    store_mat(gint + (size_t)((mu * 2 + par) * 9) * g.stride, g.stride, cb, m);
+  }
+}
+
+hipError_t launch_force_hop(const Geom& g, const double2* u18, SpF64 ell_e, SpF64 ell_o, SpF64 rho_e, SpF64 rho_o,
+                            double coef, double2* gint, hipStream_t s) {
+  hipLaunchKernelGGL(force_hop_k, dim3(blocks_for(g.V, 128)), dim3(128), 0, s, g, u18, ell_e, ell_o, rho_e, rho_o,
+                     coef, gint);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ clover force: Xi per site
+// plane p: 0 (0,1), 1 (0,2), 2 (0,3), 3 (1,2), 4 (1,3), 5 (2,3)
+// sigma block on a spin pair (a, b): k = 1: (b, a); k = 2: (-i b, i a); k = 3: (a, -b); times sign
+__device__ __forceinline__ void pauli(int k, double sgn, const Cx<double> a[3], const Cx<double> b[3],
+                                      Cx<double> oa[3], Cx<double> ob[3]) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    if (k == 1) {
+      oa[c] = sgn * b[c];
+      ob[c] = sgn * a[c];
+    } else if (k == 2) {
+      oa[c] = sgn * tmi(b[c]);
+      ob[c] = sgn * ti(a[c]);
+    } else {
+      oa[c] = sgn * a[c];
+      ob[c] = -sgn * b[c];
+    }
+  }
+}
+
+__global__ void __launch_bounds__(128) clover_xi_k(Geom g, SpF64 le, SpF64 lo, SpF64 re, SpF64 ro, double w_e,
+                                                   double w_o, double2* __restrict__ xi) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.V) return;
+  int x[4];
+  lex_coords(i, g, x);
+  const int par = parity_of(x), cb = i >> 1;
+  Spinor<double> l, r;
+  load(par ? lo : le, cb, l);
+  load(par ? ro : re, cb, r);
+  const double w = par ? w_o : w_e;
+  // (k_up, sign_up, k_dn, sign_dn) for each plane
+  const int ku[6] = {3, 2, 1, 1, 2, 3};
+  const double su[6] = {-1, 1, 1, -1, 1, 1};
+  const int kd[6] = {3, 2, 1, 1, 2, 3};
+  const double sd[6] = {-1, 1, -1, -1, -1, -1};
+#pragma unroll
+  for (int p = 0; p < 6; ++p) {
+    Spinor<double> sr;
+    pauli(ku[p], su[p], r.v[0], r.v[1], sr.v[0], sr.v[1]);
+    pauli(kd[p], sd[p], r.v[2], r.v[3], sr.v[2], sr.v[3]);
+    Mat<double> G = mzero<double>();
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) G.m[a][b] = G.m[a][b] + sr.v[s][a] * conj(l.v[s][b]);
+    const Cx<double> tr = {(G.m[0][0].re + G.m[1][1].re + G.m[2][2].re) / 3.0,
+                           (G.m[0][0].im + G.m[1][1].im + G.m[2][2].im) / 3.0};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) G.m[a][a] = G.m[a][a] - tr;
+    Mat<double> X;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) X.m[a][b] = (0.5 * w) * (G.m[a][b] + conj(G.m[b][a]));
+    store_mat(xi + (size_t)((par * 6 + p) * 9) * g.stride, g.stride, cb, X);
+  }
+}
+
+hipError_t launch_clover_xi(const Geom& g, SpF64 ell_e, SpF64 ell_o, SpF64 rho_e, SpF64 rho_o, double w_e,
+                            double w_o, double2* xi, hipStream_t s) {
+  hipLaunchKernelGGL(clover_xi_k, dim3(blocks_for(g.V, 128)), dim3(128), 0, s, g, ell_e, ell_o, rho_e, rho_o, w_e,
+                     w_o, xi);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ clover force: leaf derivatives
+__device__ __forceinline__ int plane_index(int a, int b) {  // a < b
+  return a == 0 ? b - 1 : (a == 1 ? b + 1 : 5);
+}
+__device__ __forceinline__ Mat<double> xi_at(const double2* xi, const Geom& g, int p, const int x[4]) {
+  return load_mat(xi + (size_t)((parity_of(x) * 6 + p) * 9) * g.stride, g.stride, lex(x, g) >> 1);
+}
+// Derivative matrix of the four leaves of one plaquette with respect to its
+// first link: the loop continues with L1 L2 L3, and C0..C3 are Xi at the
+// start points of (link, L1, L2, L3).  tr(dQ Xi) summed over the 4 leaves
+// equals tr(dU M) with this M.
+__device__ __forceinline__ Mat<double> insertion(const Mat<double>& L1, const Mat<double>& L2, const Mat<double>& L3,
+                                                 const Mat<double>& C0, const Mat<double>& C1, const Mat<double>& C2,
+                                                 const Mat<double>& C3) {
+  const Mat<double> L12 = mm(L1, L2), L23 = mm(L2, L3), L123 = mm(L12, L3);
+  Mat<double> m = mm(L123, C0);
+  m = madd(m, mm(C1, L123));
+  m = madd(m, mm(mm(L1, C2), L23));
+  m = madd(m, mm(mm(L12, C3), L3));
+  return m;
+}
+
+__global__ void __launch_bounds__(64) force_clover_k(Geom g, const double2* __restrict__ u18,
+                                                     const double2* __restrict__ xi, double coef,
+                                                     double2* __restrict__ gint) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 4 * g.V) return;
+  const int mu = t / g.V, i = t - mu * g.V;
+  int y[4];
+  lex_coords(i, g, y);
+  const int par = parity_of(y), cb = i >> 1;
+  Mat<double> mt = mzero<double>();
+#pragma unroll 1
+  for (int nu = 0; nu < 4; ++nu) {
+    if (nu == mu) continue;
+    const int p = mu < nu ? plane_index(mu, nu) : plane_index(nu, mu);
+    int ypm[4], ypn[4], ymn[4], ypmpn[4], ypmmn[4];
+    shift4(g, y, mu, 1, ypm);
+    shift4(g, y, nu, 1, ypn);
+    shift4(g, y, nu, -1, ymn);
+    shift4(g, ypm, nu, 1, ypmpn);
+    shift4(g, ypm, nu, -1, ypmmn);
+    Mat<double> mu_, md;
+    if (mu < nu) {
+      // link first in the plaquette at y (mu then nu)
+      mu_ = insertion(u_at(u18, g, nu, ypm), adj(u_at(u18, g, mu, ypn)), adj(u_at(u18, g, nu, y)), xi_at(xi, g, p, y),
+                      xi_at(xi, g, p, ypm), xi_at(xi, g, p, ypmpn), xi_at(xi, g, p, ypn));
+      // link reversed (third) in the plaquette at y - nu
+      md = insertion(adj(u_at(u18, g, nu, ymn)), u_at(u18, g, mu, ymn), u_at(u18, g, nu, ypmmn), xi_at(xi, g, p, ypm),
+                     xi_at(xi, g, p, y), xi_at(xi, g, p, ymn), xi_at(xi, g, p, ypmmn));
+    } else {
+      // plane (nu, mu): link second in the plaquette at y - nu
+      mu_ = insertion(adj(u_at(u18, g, nu, ypmmn)), adj(u_at(u18, g, mu, ymn)), u_at(u18, g, nu, ymn),
+                      xi_at(xi, g, p, y), xi_at(xi, g, p, ypm), xi_at(xi, g, p, ypmmn), xi_at(xi, g, p, ymn));
+      // link reversed (fourth) in the plaquette at y
+      md = insertion(u_at(u18, g, nu, y), u_at(u18, g, mu, ypn), adj(u_at(u18, g, nu, ypm)), xi_at(xi, g, p, ypm),
+                     xi_at(xi, g, p, y), xi_at(xi, g, p, ypn), xi_at(xi, g, p, ypmpn));
+    }
+    // reversed occurrences: Im tr(dU^dag M) = -Im tr(dU M^dag)
+    mt = madd(mt, msub(mu_, adj(md)));
+  }
+  // dS = coef Im tr(dU mt)  =>  G = coef * i * mt^dag
+  double2* base = gint + (size_t)((mu * 2 + par) * 9) * g.stride;
+  Mat<double> gm = load_mat(base, g.stride, cb);
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) gm.m[r][c] = gm.m[r][c] + coef * ti(conj(mt.m[c][r]));
+  store_mat(base, g.stride, cb, gm);
+}
+
+hipError_t launch_force_clover(const Geom& g, const double2* u18, const double2* xi, double coef, double2* gint,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(force_clover_k, dim3(blocks_for(4 * g.V, 64)), dim3(64), 0, s, g, u18, xi, coef, gint);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ output: G and the su(3) force
+// F^a = Re{ i tr[T^a U G^dag] } = -Im(tr[lambda^a W]) / 2, W = U G^dag
+__global__ void __launch_bounds__(128) force_out_k(Geom g, const double2* __restrict__ u18,
+                                                   const double2* __restrict__ gint, double2* __restrict__ g_user,
+                                                   double* __restrict__ f_user) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 4 * g.V) return;
+  const int i = t >> 2, mu = t & 3;
+  int x[4];
+  lex_coords(i, g, x);
+  const int par = parity_of(x), cb = i >> 1;
+  const Mat<double> G = load_mat(gint + (size_t)((mu * 2 + par) * 9) * g.stride, g.stride, cb);
+  if (g_user != nullptr) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) g_user[(size_t)t * 9 + k] = make_double2(G.m[k / 3][k % 3].re, G.m[k / 3][k % 3].im);
+  }
+  if (f_user == nullptr) return;
+  const Mat<double> U = load_mat(u18 + (size_t)((mu * 2 + par) * 9) * g.stride, g.stride, cb);
+  const Mat<double> W = mm(U, adj(G));
+  const double r3 = 0.57735026918962576451;  // 1 / sqrt(3)
+  double tr_im[8];
+  tr_im[0] = W.m[0][1].im + W.m[1][0].im;
+  tr_im[1] = (W.m[0][1] - W.m[1][0]).re;  // Im(i z) = Re z
+  tr_im[2] = W.m[0][0].im - W.m[1][1].im;
+  tr_im[3] = W.m[0][2].im + W.m[2][0].im;
+  tr_im[4] = (W.m[0][2] - W.m[2][0]).re;
+  tr_im[5] = W.m[1][2].im + W.m[2][1].im;
+  tr_im[6] = (W.m[1][2] - W.m[2][1]).re;
+  tr_im[7] = (W.m[0][0].im + W.m[1][1].im - 2.0 * W.m[2][2].im) * r3;
+#pragma unroll
+  for (int a = 0; a < 8; ++a) f_user[(size_t)t * 8 + a] = -0.5 * tr_im[a];
+}
+
+hipError_t launch_force_out(const Geom& g, const double2* u18, const double2* gint, double2* g_user,
+                            double* f_user, hipStream_t s) {
+  hipLaunchKernelGGL(force_out_k, dim3(blocks_for(4 * g.V, 128)), dim3(128), 0, s, g, u18, gint, g_user, f_user);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ HMD updates
+// exp(i Q) for Hermitian traceless Q by the Cayley-Hamilton form of
+// Morningstar and Peardon (Phys. Rev. D 69 (2004) 054501):
+// exp(iQ) = f0 + f1 Q + f2 Q^2 with f_j from c0 = det Q, c1 = tr(Q^2)/2.
+__device__ Mat<double> expi_herm(const Mat<double>& q) {
+  const Mat<double> q2 = mm(q, q);
+  const double c1 = 0.5 * (q2.m[0][0].re + q2.m[1][1].re + q2.m[2][2].re);
+  Mat<double> out;
+  if (c1 < 1e-36) {  // exp(iQ) = 1 + iQ - Q^2 / 2 + O(|Q|^3)
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        out.m[a][b] = ti(q.m[a][b]) - 0.5 * q2.m[a][b];
+        if (a == b) out.m[a][b].re += 1.0;
+      }
+    return out;
+  }
+  const Mat<double> q3 = mm(q2, q);
+  const double c0 = (q3.m[0][0].re + q3.m[1][1].re + q3.m[2][2].re) / 3.0;
+  const bool neg = c0 < 0.0;
+  const double c0a = fabs(c0);
+  const double c0max = 2.0 * pow(c1 / 3.0, 1.5);
+  double ratio = c0a / c0max;
+  ratio = ratio > 1.0 ? 1.0 : ratio;
+  const double theta = acos(ratio);
+  const double u = sqrt(c1 / 3.0) * cos(theta / 3.0);
+  const double w = sqrt(c1) * sin(theta / 3.0);
+  const double u2 = u * u, w2 = w * w;
+  const double xi0 = fabs(w) < 0.05 ? 1.0 - w2 / 6.0 * (1.0 - w2 / 20.0 * (1.0 - w2 / 42.0)) : sin(w) / w;
+  const double cw = cos(w);
+  const Cx<double> e2iu = {cos(2.0 * u), sin(2.0 * u)}, emiu = {cos(u), -sin(u)};
+  Cx<double> h0 = (u2 - w2) * e2iu + emiu * Cx<double>{8.0 * u2 * cw, 2.0 * u * (3.0 * u2 + w2) * xi0};
+  Cx<double> h1 = (2.0 * u) * e2iu - emiu * Cx<double>{2.0 * u * cw, -(3.0 * u2 - w2) * xi0};
+  Cx<double> h2 = e2iu - emiu * Cx<double>{cw, 3.0 * u * xi0};
+  const double den = 1.0 / (9.0 * u2 - w2);
+  Cx<double> f0 = den * h0, f1 = den * h1, f2 = den * h2;
+  if (neg) {  // f_j(-c0) = (-1)^j conj(f_j(c0))
+    f0 = conj(f0);
+    f1 = -conj(f1);
+    f2 = conj(f2);
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      out.m[a][b] = f1 * q.m[a][b] + f2 * q2.m[a][b];
+      if (a == b) out.m[a][b] = out.m[a][b] + f0;
+    }
+  return out;
+}
+
+// U_mu(x) <- exp(i c P_mu(x)) U_mu(x), P = sum_a P^a lambda^a / 2
+__global__ void __launch_bounds__(128) link_exp_k(Geom g, double2* __restrict__ u18, const double* __restrict__ p_user,
+                                                  double c) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 4 * g.V) return;
+  const int i = t >> 2, mu = t & 3;
+  int x[4];
+  lex_coords(i, g, x);
+  const int par = parity_of(x), cb = i >> 1;
+  double P[8];
+#pragma unroll
+  for (int a = 0; a < 8; ++a) P[a] = 0.5 * c * p_user[(size_t)t * 8 + a];
+  const double r3 = 0.57735026918962576451;
+  Mat<double> q;
+  q.m[0][0] = {P[2] + P[7] * r3, 0.0};
+  q.m[1][1] = {-P[2] + P[7] * r3, 0.0};
+  q.m[2][2] = {-2.0 * P[7] * r3, 0.0};
+  q.m[0][1] = {P[0], -P[1]};
+  q.m[1][0] = {P[0], P[1]};
+  q.m[0][2] = {P[3], -P[4]};
+  q.m[2][0] = {P[3], P[4]};
+  q.m[1][2] = {P[5], -P[6]};
+  q.m[2][1] = {P[5], P[6]};
+  double2* base = u18 + (size_t)((mu * 2 + par) * 9) * g.stride;
+  const Mat<double> U = load_mat(base, g.stride, cb);
+  store_mat(base, g.stride, cb, mm(expi_herm(q), U));
+}
+
+hipError_t launch_link_exp(const Geom& g, double2* u18, const double* p_user, double c, hipStream_t s) {
+  hipLaunchKernelGGL(link_exp_k, dim3(blocks_for(4 * g.V, 128)), dim3(128), 0, s, g, u18, p_user, c);
+  return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(256) mom_update_k(int n, double* __restrict__ p, const double* __restrict__ f,
+                                                    double dt) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  p[i] -= dt * f[i];
+}
+hipError_t launch_mom_update(const Geom& g, double* p_user, const double* f_user, double dt, hipStream_t s) {
+  const int n = 32 * g.V;
+  hipLaunchKernelGGL(mom_update_k, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, p_user, f_user, dt);
+  return hipGetLastError();
+}
+
+}  // namespace qcd

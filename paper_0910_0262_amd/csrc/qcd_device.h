@@ -1,0 +1,556 @@
+// Device-side building blocks for the gfx950 Wilson-clover kernels:
+// complex arithmetic, spinor / link / clover register types, the
+// structure-of-arrays field accessors (FP64, FP32, binary16 + scale), the
+// checkerboard geometry, wave64 block reductions and the XCD-aware block
+// order.  Everything here is header-only and used by the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace qcd {
+
+// ------------------------------------------------------------------ complex
+template <typename R>
+struct Cx {
+  R re, im;
+};
+
+template <typename R>
+__device__ __forceinline__ Cx<R> cx(R a, R b) { return Cx<R>{a, b}; }
+template <typename R>
+__device__ __forceinline__ Cx<R> operator+(Cx<R> a, Cx<R> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename R>
+__device__ __forceinline__ Cx<R> operator-(Cx<R> a, Cx<R> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename R>
+__device__ __forceinline__ Cx<R> operator-(Cx<R> a) { return {-a.re, -a.im}; }
+template <typename R>
+__device__ __forceinline__ Cx<R> operator*(Cx<R> a, Cx<R> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename R>
+__device__ __forceinline__ Cx<R> operator*(R s, Cx<R> a) { return {s * a.re, s * a.im}; }
+template <typename R>
+__device__ __forceinline__ Cx<R> conj(Cx<R> a) { return {a.re, -a.im}; }
+// conj(a) * b
+template <typename R>
+__device__ __forceinline__ Cx<R> cmulc(Cx<R> a, Cx<R> b) {
+  return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+}
+template <typename R>
+__device__ __forceinline__ Cx<R> ti(Cx<R> a) { return {-a.im, a.re}; }   // i a
+template <typename R>
+__device__ __forceinline__ Cx<R> tmi(Cx<R> a) { return {a.im, -a.re}; }  // -i a
+template <typename R>
+__device__ __forceinline__ R norm2(Cx<R> a) { return a.re * a.re + a.im * a.im; }
+
+// ------------------------------------------------------------------ register types
+template <typename R>
+struct Spinor {
+  Cx<R> v[4][3];  // [spin][colour]
+};
+template <typename R>
+struct Half {
+  Cx<R> h[2][3];
+};
+template <typename R>
+struct Mat {
+  Cx<R> m[3][3];  // [row][col]
+};
+
+template <typename R>
+__device__ __forceinline__ void zero(Spinor<R>& s) {
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) s.v[a][c] = {R(0), R(0)};
+}
+template <typename R>
+__device__ __forceinline__ void neg_lower(Spinor<R>& s) {
+#pragma unroll
+  for (int a = 2; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) s.v[a][c] = -s.v[a][c];
+}
+template <typename R>
+__device__ __forceinline__ double site_norm2(const Spinor<R>& s) {
+  double n = 0.0;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) n += double(s.v[a][c].re) * double(s.v[a][c].re) + double(s.v[a][c].im) * double(s.v[a][c].im);
+  return n;
+}
+
+// U h, colour matrix times the two colour vectors of a half spinor
+template <typename R>
+__device__ __forceinline__ void mul_mat(const Mat<R>& u, const Half<R>& in, Half<R>& out) {
+#pragma unroll
+  for (int k = 0; k < 2; ++k)
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+      out.h[k][a] = u.m[a][0] * in.h[k][0] + u.m[a][1] * in.h[k][1] + u.m[a][2] * in.h[k][2];
+}
+// U^dag h
+template <typename R>
+__device__ __forceinline__ void mul_adj(const Mat<R>& u, const Half<R>& in, Half<R>& out) {
+#pragma unroll
+  for (int k = 0; k < 2; ++k)
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+      out.h[k][a] = cmulc(u.m[0][a], in.h[k][0]) + cmulc(u.m[1][a], in.h[k][1]) + cmulc(u.m[2][a], in.h[k][2]);
+}
+
+template <typename R>
+__device__ __forceinline__ Mat<R> mm(const Mat<R>& a, const Mat<R>& b) {
+  Mat<R> c;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) c.m[i][j] = a.m[i][0] * b.m[0][j] + a.m[i][1] * b.m[1][j] + a.m[i][2] * b.m[2][j];
+  return c;
+}
+template <typename R>
+__device__ __forceinline__ Mat<R> adj(const Mat<R>& a) {
+  Mat<R> c;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) c.m[i][j] = conj(a.m[j][i]);
+  return c;
+}
+template <typename R>
+__device__ __forceinline__ Mat<R> madd(const Mat<R>& a, const Mat<R>& b) {
+  Mat<R> c;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) c.m[i][j] = a.m[i][j] + b.m[i][j];
+  return c;
+}
+template <typename R>
+__device__ __forceinline__ Mat<R> msub(const Mat<R>& a, const Mat<R>& b) {
+  Mat<R> c;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) c.m[i][j] = a.m[i][j] - b.m[i][j];
+  return c;
+}
+template <typename R>
+__device__ __forceinline__ Mat<R> mzero() {
+  Mat<R> c;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) c.m[i][j] = {R(0), R(0)};
+  return c;
+}
+
+// ------------------------------------------------------------------ geometry
+// Lattice extents and the checkerboard stride of the structure-of-arrays
+// fields.  cb = i / 2 for lexicographic site i = x + Lx (y + Ly (z + Lz t)).
+struct Geom {
+  int X[4];      // Lx, Ly, Lz, Lt
+  int Xh;        // Lx / 2
+  int V, Vh;
+  int stride;    // element stride between components of one field (>= Vh)
+  int tb;        // +1 periodic / -1 antiperiodic in time
+};
+
+__device__ __forceinline__ void cb_coords(int cb, int par, const Geom& g, int x[4]) {
+  int xh = cb % g.Xh;
+  int r = cb / g.Xh;
+  x[1] = r % g.X[1];
+  r /= g.X[1];
+  x[2] = r % g.X[2];
+  x[3] = r / g.X[2];
+  x[0] = 2 * xh + ((x[1] + x[2] + x[3] + par) & 1);
+}
+__device__ __forceinline__ int lex(const int x[4], const Geom& g) {
+  return x[0] + g.X[0] * (x[1] + g.X[1] * (x[2] + g.X[2] * x[3]));
+}
+__device__ __forceinline__ void lex_coords(int i, const Geom& g, int x[4]) {
+  x[0] = i % g.X[0];
+  int r = i / g.X[0];
+  x[1] = r % g.X[1];
+  r /= g.X[1];
+  x[2] = r % g.X[2];
+  x[3] = r / g.X[2];
+}
+__device__ __forceinline__ int parity_of(const int x[4]) { return (x[0] + x[1] + x[2] + x[3]) & 1; }
+
+// Workgroups are dealt round-robin to the 8 XCDs (each with its own L2).
+// Map hardware block b to a logical block so that XCD k gets one contiguous
+// range of logical blocks: neighbouring sites then share an L2.
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+  const int q = nb >> 3, rem = nb & 7;
+  const int xcd = b & 7, k = b >> 3;
+  return (xcd < rem) ? xcd * (q + 1) + k : rem * (q + 1) + (xcd - rem) * q + k;
+}
+
+// ------------------------------------------------------------------ binary16
+typedef _Float16 h4_t __attribute__((ext_vector_type(4)));
+typedef _Float16 h8_t __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ h8_t as_h8(uint4 w) {
+  h8_t h;
+  __builtin_memcpy(&h, &w, 16);
+  return h;
+}
+__device__ __forceinline__ uint4 from_h8(h8_t h) {
+  uint4 w;
+  __builtin_memcpy(&w, &h, 16);
+  return w;
+}
+__device__ __forceinline__ h4_t as_h4(uint2 w) {
+  h4_t h;
+  __builtin_memcpy(&h, &w, 8);
+  return h;
+}
+__device__ __forceinline__ uint2 from_h4(h4_t h) {
+  uint2 w;
+  __builtin_memcpy(&w, &h, 8);
+  return w;
+}
+
+// ------------------------------------------------------------------ spinor fields
+// Each field is one checkerboard, structure of arrays: component chunk k of
+// site cb lives at p[k * stride + cb], so a wavefront's loads of one chunk
+// are contiguous.
+struct SpF64 {   // 12 chunks of double2 (one complex each), 192 B / site
+  double2* p;
+  int stride;
+};
+struct SpF32 {   // 6 chunks of float4 (two complex each), 96 B / site
+  float4* p;
+  int stride;
+};
+struct SpH {     // 3 chunks of 8 x binary16 + one float scale, 52 B / site
+  uint4* p;
+  float* s;
+  int stride;
+};
+
+template <typename R>
+__device__ __forceinline__ void load(const SpF64& f, int i, Spinor<R>& v) {
+#pragma unroll
+  for (int k = 0; k < 12; ++k) {
+    double2 d = f.p[(size_t)k * f.stride + i];
+    v.v[k / 3][k % 3] = {R(d.x), R(d.y)};
+  }
+}
+template <typename R>
+__device__ __forceinline__ void store(const SpF64& f, int i, const Spinor<R>& v) {
+#pragma unroll
+  for (int k = 0; k < 12; ++k)
+    f.p[(size_t)k * f.stride + i] = make_double2(double(v.v[k / 3][k % 3].re), double(v.v[k / 3][k % 3].im));
+}
+template <typename R>
+__device__ __forceinline__ void load(const SpF32& f, int i, Spinor<R>& v) {
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    float4 d = f.p[(size_t)k * f.stride + i];
+    v.v[(2 * k) / 3][(2 * k) % 3] = {R(d.x), R(d.y)};
+    v.v[(2 * k + 1) / 3][(2 * k + 1) % 3] = {R(d.z), R(d.w)};
+  }
+}
+template <typename R>
+__device__ __forceinline__ void store(const SpF32& f, int i, const Spinor<R>& v) {
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const Cx<R> a = v.v[(2 * k) / 3][(2 * k) % 3], b = v.v[(2 * k + 1) / 3][(2 * k + 1) % 3];
+    f.p[(size_t)k * f.stride + i] = make_float4(float(a.re), float(a.im), float(b.re), float(b.im));
+  }
+}
+template <typename R>
+__device__ __forceinline__ void load(const SpH& f, int i, Spinor<R>& v) {
+  const float s = f.s[i];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    h8_t h = as_h8(f.p[(size_t)k * f.stride + i]);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int c = 4 * k + j;  // complex component 0..11
+      v.v[c / 3][c % 3] = {R(float(h[2 * j]) * s), R(float(h[2 * j + 1]) * s)};
+    }
+  }
+}
+// binary16 encoder: scale = max |component| over the 24 reals (float32),
+// code = rn_binary16(component * (1 / scale)); an all-zero spinor keeps scale 0.
+template <typename R>
+__device__ __forceinline__ float encode_site(const Spinor<R>& v, h8_t out[3]) {
+  float m = 0.f;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) m = fmaxf(m, fmaxf(fabsf(float(v.v[a][c].re)), fabsf(float(v.v[a][c].im))));
+  const float inv = m > 0.f ? 1.0f / m : 0.f;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int c = 4 * k + j;
+      out[k][2 * j] = (_Float16)(float(v.v[c / 3][c % 3].re) * inv);
+      out[k][2 * j + 1] = (_Float16)(float(v.v[c / 3][c % 3].im) * inv);
+    }
+  }
+  return m;
+}
+template <typename R>
+__device__ __forceinline__ void store(const SpH& f, int i, const Spinor<R>& v) {
+  h8_t h[3];
+  const float m = encode_site(v, h);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) f.p[(size_t)k * f.stride + i] = from_h8(h[k]);
+  f.s[i] = m;
+}
+
+// ------------------------------------------------------------------ link fields
+// Link U_mu(x) for x of parity par and checkerboard index cb.  Chunk k of
+// (mu, par) lives at p[((mu * 2 + par) * NC + k) * stride + cb].
+template <int NC>  // 9 = full 18-real matrix, 6 = two rows (12 reals), third rebuilt
+struct LinkF64 {
+  const double2* p;
+  int stride;
+};
+struct LinkH12 {   // two rows as 12 x binary16, 3 chunks of 4 halves (24 B / link)
+  const uint2* p;
+  int stride;
+};
+
+template <typename R>
+__device__ __forceinline__ void reconstruct_row2(Mat<R>& u) {
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const int j1 = (j + 1) % 3, j2 = (j + 2) % 3;
+    u.m[2][j] = conj(u.m[0][j1] * u.m[1][j2] - u.m[0][j2] * u.m[1][j1]);
+  }
+}
+template <typename R, int NC>
+__device__ __forceinline__ void load_link(const LinkF64<NC>& f, int mu, int par, int i, Mat<R>& u) {
+  const double2* base = f.p + (size_t)((mu * 2 + par) * NC) * f.stride + i;
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    double2 d = base[(size_t)k * f.stride];
+    u.m[k / 3][k % 3] = {R(d.x), R(d.y)};
+  }
+  if (NC == 6) reconstruct_row2(u);
+}
+template <typename R>
+__device__ __forceinline__ void load_link(const LinkH12& f, int mu, int par, int i, Mat<R>& u) {
+  const uint2* base = f.p + (size_t)((mu * 2 + par) * 3) * f.stride + i;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    h4_t h = as_h4(base[(size_t)k * f.stride]);
+    const int c0 = 2 * k, c1 = 2 * k + 1;  // complex entries 0..5 of rows 0, 1
+    u.m[c0 / 3][c0 % 3] = {R(float(h[0])), R(float(h[1]))};
+    u.m[c1 / 3][c1 % 3] = {R(float(h[2])), R(float(h[3]))};
+  }
+  reconstruct_row2(u);
+}
+
+// ------------------------------------------------------------------ clover fields
+// Two Hermitian 6x6 blocks per site (spins {0,1} and {2,3}, index 3 s + c).
+// Packed per block: 6 real diagonal entries then the 15 upper off-diagonal
+// entries in row-major order, 36 reals.
+struct CloverNone {};
+struct CloverF64 {   // 36 chunks of double2 per site: [block][18]
+  const double2* p;
+  int stride;
+};
+struct CloverF32 {   // 18 chunks of float4 per site: reals [block * 36 + r]
+  const float4* p;
+  int stride;
+};
+struct CloverH {     // 9 chunks of 8 x binary16 + per-block float scale
+  const uint4* p;
+  const float2* s;
+  int stride;
+};
+
+__host__ __device__ constexpr int offd(int i, int j) { return i * (11 - i) / 2 + (j - i - 1); }  // i < j
+
+template <typename R>
+struct Block {
+  R d[6];
+  Cx<R> o[15];
+};
+
+template <typename R>
+__device__ __forceinline__ void load_block(const CloverF64& c, int i, int b, Block<R>& blk) {
+  const double2* base = c.p + (size_t)(b * 18) * c.stride + i;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    double2 d = base[(size_t)k * c.stride];
+    blk.d[2 * k] = R(d.x);
+    blk.d[2 * k + 1] = R(d.y);
+  }
+#pragma unroll
+  for (int k = 0; k < 15; ++k) {
+    double2 d = base[(size_t)(3 + k) * c.stride];
+    blk.o[k] = {R(d.x), R(d.y)};
+  }
+}
+template <typename R>
+__device__ __forceinline__ void load_block(const CloverF32& c, int i, int b, Block<R>& blk) {
+  float r[36];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    float4 d = c.p[(size_t)(b * 9 + k) * c.stride + i];
+    r[4 * k] = d.x;
+    r[4 * k + 1] = d.y;
+    r[4 * k + 2] = d.z;
+    r[4 * k + 3] = d.w;
+  }
+#pragma unroll
+  for (int k = 0; k < 6; ++k) blk.d[k] = R(r[k]);
+#pragma unroll
+  for (int k = 0; k < 15; ++k) blk.o[k] = {R(r[6 + 2 * k]), R(r[7 + 2 * k])};
+}
+template <typename R>
+__device__ __forceinline__ void load_block(const CloverH& c, int i, int b, Block<R>& blk) {
+  // 72 halves per site = 9 chunks; block b owns halves [36 b, 36 b + 36)
+  const float2 sc = c.s[i];
+  const float s = b == 0 ? sc.x : sc.y;
+  float r[36];
+#pragma unroll
+  for (int k = 0; k < 36; ++k) r[k] = 0.f;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    const int lo = 8 * k, hi = 8 * k + 8;  // half indices of this chunk
+    if (hi <= 36 * b || lo >= 36 * b + 36) continue;
+    h8_t h = as_h8(c.p[(size_t)k * c.stride + i]);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int q = lo + j - 36 * b;
+      if (q >= 0 && q < 36) r[q] = float(h[j]) * s;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 6; ++k) blk.d[k] = R(r[k]);
+#pragma unroll
+  for (int k = 0; k < 15; ++k) blk.o[k] = {R(r[6 + 2 * k]), R(r[7 + 2 * k])};
+}
+
+// v <- A v for one 6-vector (spins 2b, 2b+1)
+template <typename R>
+__device__ __forceinline__ void block_mv(const Block<R>& a, Cx<R> v[6]) {
+  Cx<R> out[6];
+#pragma unroll
+  for (int r = 0; r < 6; ++r) {
+    Cx<R> s = a.d[r] * v[r];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      if (c > r) s = s + a.o[offd(r, c)] * v[c];
+      if (c < r) s = s + cmulc(a.o[offd(c, r)], v[c]);
+    }
+    out[r] = s;
+  }
+#pragma unroll
+  for (int r = 0; r < 6; ++r) v[r] = out[r];
+}
+
+template <typename R, class CL>
+__device__ __forceinline__ void apply_clover(const CL& c, int i, Spinor<R>& s) {
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    Block<R> blk;
+    load_block(c, i, b, blk);
+    Cx<R> v[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) v[k] = s.v[2 * b + k / 3][k % 3];
+    block_mv(blk, v);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) s.v[2 * b + k / 3][k % 3] = v[k];
+  }
+}
+
+// ------------------------------------------------------------------ spin projection
+// Upper two spin components h of (1 + S gamma_mu) psi, S = -1 or +1, in the
+// chiral basis; the lower two are a fixed linear map of h (reconstruct()).
+template <int MU, int S, typename R>
+__device__ __forceinline__ void project(const Spinor<R>& p, Half<R>& h) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const Cx<R> u0 = p.v[0][c], u1 = p.v[1][c], d0 = p.v[2][c], d1 = p.v[3][c];
+    if (MU == 0) {
+      h.h[0][c] = S < 0 ? u0 + ti(d1) : u0 - ti(d1);
+      h.h[1][c] = S < 0 ? u1 + ti(d0) : u1 - ti(d0);
+    } else if (MU == 1) {
+      h.h[0][c] = S < 0 ? u0 + d1 : u0 - d1;
+      h.h[1][c] = S < 0 ? u1 - d0 : u1 + d0;
+    } else if (MU == 2) {
+      h.h[0][c] = S < 0 ? u0 + ti(d0) : u0 - ti(d0);
+      h.h[1][c] = S < 0 ? u1 - ti(d1) : u1 + ti(d1);
+    } else {
+      h.h[0][c] = S < 0 ? u0 - d0 : u0 + d0;
+      h.h[1][c] = S < 0 ? u1 - d1 : u1 + d1;
+    }
+  }
+}
+// acc += (h, lower(h)) for the projector (1 + S gamma_mu)
+template <int MU, int S, typename R>
+__device__ __forceinline__ void accumulate(Spinor<R>& a, const Half<R>& h) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const Cx<R> h0 = h.h[0][c], h1 = h.h[1][c];
+    a.v[0][c] = a.v[0][c] + h0;
+    a.v[1][c] = a.v[1][c] + h1;
+    if (MU == 0) {
+      a.v[2][c] = a.v[2][c] + (S < 0 ? tmi(h1) : ti(h1));
+      a.v[3][c] = a.v[3][c] + (S < 0 ? tmi(h0) : ti(h0));
+    } else if (MU == 1) {
+      a.v[2][c] = a.v[2][c] + (S < 0 ? -h1 : h1);
+      a.v[3][c] = a.v[3][c] + (S < 0 ? h0 : -h0);
+    } else if (MU == 2) {
+      a.v[2][c] = a.v[2][c] + (S < 0 ? tmi(h0) : ti(h0));
+      a.v[3][c] = a.v[3][c] + (S < 0 ? ti(h1) : tmi(h1));
+    } else {
+      a.v[2][c] = a.v[2][c] + (S < 0 ? -h0 : h0);
+      a.v[3][c] = a.v[3][c] + (S < 0 ? -h1 : h1);
+    }
+  }
+}
+
+// ------------------------------------------------------------------ reductions
+// Sum of v over the workgroup (wave64 shuffles, then LDS); the result is
+// written by thread 0 to partial[slot].  Every thread of the block must call it.
+__device__ __forceinline__ void block_sum_store(double v, double* partial, int slot) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  __shared__ double red[16];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int k = 0; k < nw; ++k) s += red[k];
+    partial[slot] = s;
+  }
+}
+
+// Fixed-order sum of n partials by one workgroup; the result is returned to
+// every thread.  Deterministic for a given n and blockDim.
+__device__ __forceinline__ double block_sum_partials(const double* p, int n) {
+  double s = 0.0;
+  for (int k = threadIdx.x; k < n; k += blockDim.x) s += p[k];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  __shared__ double red[16];
+  __shared__ double total;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) red[w] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int k = 0; k < nw; ++k) t += red[k];
+    total = t;
+  }
+  __syncthreads();
+  return total;
+}
+
+}  // namespace qcd

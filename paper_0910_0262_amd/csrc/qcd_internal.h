@@ -1,0 +1,121 @@
+// Internal interface between the C-ABI host code (api.hip) and the kernel
+// translation units: the on-device solver state, field references and the
+// launch functions.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "qcd_device.h"
+
+namespace qcd {
+
+// Scalars of the CG recurrence, resident in device memory so that alpha and
+// beta never travel to the host.  Kernels of an iteration return at once
+// when `halt` is set (converged or non-finite), which lets the host keep a
+// few iterations in flight and stop the recurrence without a round trip.
+struct CgState {
+  double rr;       // |r_k|^2 of the current recurrence residual
+  double qq;       // |Mhat p|^2
+  double alpha, beta;
+  double stop2;    // tol^2 |rhs|^2
+  double maxrr;    // max |r|^2 since the last reliable update
+  double delta2;   // delta_reliable^2
+  double rr_hi;    // last FP64 residual norm^2
+  double scalar;   // generic reduction result (dot products, norms)
+  int iter, max_iter;
+  int halt, done, need_ru, nan, do_x, do_p, mixed, ru_count;
+};
+
+enum SpKind { SP_NONE = 0, SP_F64 = 1, SP_F32 = 2, SP_H = 3 };
+struct SpRef {
+  int kind;
+  void* p;
+  float* s;  // per-site scale (SP_H)
+};
+enum LinkKind { LK_F64_18 = 0, LK_F64_12 = 1, LK_H12 = 2 };
+enum ClovKind { CL_NONE = 0, CL_F64 = 1, CL_F32 = 2, CL_H = 3 };
+struct ClovRef {
+  int kind;
+  const void* p;
+  const float2* s;
+};
+
+// out(x) = [post ? C(x) : 1] ( [site term] + c * g5^g5out H g5^g5in in )(x)
+// on every site x of parity par_out, where the site term is 0, s(x), or A(x) s(x),
+// followed by an epilogue: 0 store; 1 store and |out|^2 partials;
+// 2 dst = y + a out (a = -alpha from the state if a_from_state), store dst
+// into `out`, |dst|^2 partials.
+struct DslashOp {
+  int par_out;
+  SpRef in, site, out, y;
+  int link_kind;
+  const void* links;
+  ClovRef cpre, cpost;
+  double c;
+  int site_mode;  // 0 none, 1 plain, 2 multiplied by cpre
+  int post;
+  int epi;
+  double a;
+  int a_from_state;
+  int g5in, g5out;
+  const CgState* st;
+  double* partial;
+};
+
+inline int blocks_for(int n, int block) { return (n + block - 1) / block; }
+
+// ---- dslash.hip
+hipError_t launch_dslash(const Geom& g, const DslashOp& op, int block, hipStream_t s);
+hipError_t launch_clover_apply(const Geom& g, SpF64 in, SpF64 out, const double2* clov, hipStream_t s);
+
+// ---- blas.hip
+hipError_t launch_pack_spinor_full(const Geom& g, const double2* user, SpF64 e, SpF64 o, hipStream_t s);
+hipError_t launch_unpack_spinor_full(const Geom& g, SpF64 e, SpF64 o, double2* user, hipStream_t s);
+hipError_t launch_pack_spinor_cb(const Geom& g, const double2* user, SpF64 f, hipStream_t s);
+hipError_t launch_unpack_spinor_cb(const Geom& g, SpF64 f, double2* user, hipStream_t s);
+hipError_t launch_pack_gauge(const Geom& g, const double2* user, double2* u18, hipStream_t s);
+hipError_t launch_unpack_gauge(const Geom& g, const double2* u18, double2* user, hipStream_t s);
+hipError_t launch_derive_links(const Geom& g, const double2* u18, double2* u12, uint2* uh, hipStream_t s);
+hipError_t launch_pack_clover(const Geom& g, const double2* user, double2* clov, hipStream_t s);
+hipError_t launch_unpack_clover(const Geom& g, const double2* clov, double2* user, int n_par, int par0,
+                                hipStream_t s);
+hipError_t launch_norm2(const Geom& g, SpRef x, double* partial, int block, hipStream_t s);
+hipError_t launch_dot_re(const Geom& g, SpF64 a, SpF64 b, double* partial, int block, hipStream_t s);
+hipError_t launch_fin_scalar(CgState* st, const double* partial, int n, hipStream_t s);
+hipError_t launch_fin_init(CgState* st, const double* partial, int n, double tol, double delta, int max_iter,
+                           int mixed, CgState* mbox, int slot, hipStream_t s);
+hipError_t launch_fin_alpha(CgState* st, const double* partial, int n, hipStream_t s);
+hipError_t launch_fin_beta(CgState* st, const double* partial, int n, CgState* mbox, int slot, hipStream_t s);
+hipError_t launch_fin_ru(CgState* st, const double* partial, int n, int restart, CgState* mbox, int slot,
+                         hipStream_t s);
+hipError_t launch_xp_update_f64(const Geom& g, const CgState* st, SpF64 x, SpF64 p, SpF64 r, int block,
+                                hipStream_t s);
+hipError_t launch_xp_update_h(const Geom& g, const CgState* st, SpF32 x, SpH p, SpH r, int block, hipStream_t s);
+hipError_t launch_p_restart_f64(const Geom& g, const CgState* st, SpF64 p, SpF64 r, int block, hipStream_t s);
+hipError_t launch_ru_accum(const Geom& g, SpF64 xhi, SpF32 xlo, int block, hipStream_t s);
+hipError_t launch_convert(const Geom& g, SpRef src, SpRef dst, int block, hipStream_t s);
+hipError_t launch_zero(const Geom& g, SpRef x, int block, hipStream_t s);
+hipError_t launch_encode_half(int n, const double2* user, uint4* codes, float* scale, hipStream_t s);
+hipError_t launch_stream_copy(const uint4* src, uint4* dst, uint64_t n16, hipStream_t s);
+
+// ---- clover.hip
+hipError_t launch_clover_build(const Geom& g, const double2* u18, double kappa, double csw, double2* clov,
+                               hipStream_t s);
+hipError_t launch_clover_invert(const Geom& g, const double2* clov, double2* clov_inv, float4* clov32_e,
+                                float4* clovinv32_o, uint4* clovh_e, float2* clovh_es, uint4* clovinvh_o,
+                                float2* clovinvh_os, int* status, hipStream_t s);
+
+// ---- force.hip
+hipError_t launch_force_hop(const Geom& g, const double2* u18, SpF64 ell_e, SpF64 ell_o, SpF64 rho_e,
+                            SpF64 rho_o, double coef, double2* gint, hipStream_t s);
+hipError_t launch_clover_xi(const Geom& g, SpF64 ell_e, SpF64 ell_o, SpF64 rho_e, SpF64 rho_o, double w_e,
+                            double w_o, double2* xi, hipStream_t s);
+hipError_t launch_force_clover(const Geom& g, const double2* u18, const double2* xi, double coef, double2* gint,
+                               hipStream_t s);
+hipError_t launch_force_out(const Geom& g, const double2* u18, const double2* gint, double2* g_user,
+                            double* f_user, hipStream_t s);
+hipError_t launch_link_exp(const Geom& g, double2* u18, const double* p_user, double c, hipStream_t s);
+hipError_t launch_mom_update(const Geom& g, double* p_user, const double* f_user, double dt, hipStream_t s);
+
+}  // namespace qcd

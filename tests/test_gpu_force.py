@@ -1,0 +1,132 @@
+"""GPU parity of the action, its gauge gradient G, the su(3) force F and one HMD
+step against the oracle; the autograd path against the oracle and against
+central finite differences of the GPU action.
+
+Bar (BASELINE target): force relative error <= 1e-9 against the FP64 oracle,
+with the solves inside at tol 1e-12 (a solve to tol t moves the force by
+O(cond * t))."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from oracle.force import force_matrix
+from paper_0910_0262_amd import CloverForce, Lattice, capi, synth
+
+from ._gpu_helpers import make_case, max_rel, rel_err, to_dev
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    ((4, 4, 4, 4), 0.3, 0.12, 1.0, 0),
+    ((4, 4, 4, 4), 0.3, 0.12, 0.0, 1),
+    ((6, 4, 2, 8), 0.5, 0.124, 1.3, 2),
+    ((8, 8, 8, 8), 0.3, 0.125, 1.0, 3),
+]
+IDS = ["4^4", "4^4-csw0", "6x4x2x8", "8^4"]
+
+
+@pytest.fixture(scope="module", params=CASES, ids=IDS)
+def case(request):
+    dims, w, k, c, seed = request.param
+    print(f"[force case dims={dims} width={w} kappa={k} csw={c} seed={seed}]", flush=True)
+    lat, setup, u, ud = make_case(dims, w, k, c, seed)
+    xi = torch.as_tensor(synth.heatbath_xi(dims, seed))
+    phi = setup.Mhat_dag(xi)
+    S, G, X, _ = O.action_and_gradient(torch.as_tensor(u), k, c, phi, tol=1e-14)
+    F = O.project_force(torch.as_tensor(u), G)
+    yield dims, lat, u, ud, phi, (S, G, F, X), (k, c)
+    lat.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_force_parity(case, prec):
+    dims, lat, u, ud, phi, (S, G, F, X), _ = case
+    S_g, G_g, F_g, X_g, st = lat.action_force(to_dev(phi), prec=prec, tol=1e-12)
+    print(f"  {prec}: iters={st['iters']} S={S_g:.10e} oracle S={S:.10e}", flush=True)
+    assert abs(S_g - S) < 1e-10 * abs(S)
+    assert rel_err(X_g, X) < 1e-10
+    assert max_rel(G_g, G) < 1e-9
+    assert max_rel(F_g, F) < 1e-9
+    # F is the su(3) projection of G: Hermitian traceless coefficients of (i/2) TA(U G^dag)
+    Fm = force_matrix(F_g.cpu())
+    assert torch.abs(Fm - Fm.conj().transpose(-1, -2)).max() < 1e-12
+
+
+def test_autograd_backward(case):
+    dims, lat, u, ud, phi, (S, G, F, X), (k, c) = case
+    U = ud.clone().requires_grad_(True)
+    ph = to_dev(phi).requires_grad_(True)
+    s = CloverForce.apply(U, ph, lat, "fp64", 1e-12)
+    (3.0 * s).backward()
+    assert abs(float(s) - S) < 1e-10 * abs(S)
+    assert max_rel(U.grad, 3.0 * G) < 1e-9
+    assert rel_err(ph.grad, 6.0 * X) < 1e-10
+
+
+def test_autograd_vs_finite_differences():
+    """Central differences (eps = 1e-5) of the GPU action along su(3) generators, 4^4."""
+    dims, kappa, csw = (4, 4, 4, 4), 0.12, 1.0
+    u = synth.random_su3_field(dims, 0.3, 0)
+    lat = Lattice(dims, kappa, csw)
+    ud = to_dev(u)
+    lat.load_gauge(ud)
+    xi = to_dev(synth.heatbath_xi(dims, 0))
+    phi = lat.apply("Mhatdag", xi)
+    S0, G, F, X, _ = lat.action_force(phi, tol=1e-13)
+    lam = O.gell_mann()
+    eps = 1e-5
+    scale = float(torch.abs(F).max())
+    for site, mu, a in [((0, 0, 0, 0), 0, 0), ((1, 2, 3, 0), 3, 4), ((3, 1, 0, 2), 1, 7)]:
+        vals = []
+        for sgn in (1, -1):
+            up = u.copy()
+            e = torch.linalg.matrix_exp(1j * sgn * eps * lam[a] / 2).numpy()
+            up[site + (mu,)] = e @ u[site + (mu,)]
+            lat.load_gauge(to_dev(up))
+            # variational action 2 Re phi^dag X - |Mhat X|^2: error quadratic in the residual
+            _, _, _, x, _ = lat.action_force(phi, tol=1e-13, want_F=False)
+            y = lat.apply("Mhat", x)
+            vals.append(float(2.0 * torch.vdot(phi.reshape(-1), x.reshape(-1)).real - torch.vdot(y.reshape(-1), y.reshape(-1)).real))
+        fd = (vals[0] - vals[1]) / (2 * eps)
+        assert abs(fd - float(F[site + (mu, a)])) < 1e-6 * scale
+    lat.close()
+
+
+def test_hmd_step_parity():
+    dims, kappa, csw, dt = (4, 4, 4, 4), 0.125, 1.0, 0.02
+    u0 = synth.random_su3_field(dims, 0.3, 0)
+    p0 = synth.momenta(dims, 0)
+    xi = synth.heatbath_xi(dims, 0)
+    ref = O.hmd_step(torch.as_tensor(u0), torch.as_tensor(p0), torch.as_tensor(xi), dt, kappa, csw, tol=1e-14)
+    lat = Lattice(dims, kappa, csw)
+    U = to_dev(u0)
+    P = to_dev(p0)
+    S, st = lat.hmd_step(U, P, to_dev(xi), dt, prec="fp64", tol=1e-12)
+    assert abs(S - ref["S"]) < 1e-10 * abs(ref["S"])
+    assert max_rel(U, ref["U"]) < 1e-9
+    assert max_rel(P, ref["P"]) < 1e-9
+    # unitarity is kept by the exponential update
+    uu = U.conj().transpose(-1, -2) @ U
+    assert torch.abs(uu - torch.eye(3, dtype=torch.complex128, device="cuda")).max() < 1e-13
+    # reversibility: (U1, -P1) with the same xi returns to (U0, -P0)
+    P.neg_()
+    lat.hmd_step(U, P, to_dev(xi), dt, prec="fp64", tol=1e-12)
+    assert torch.abs(U.cpu() - torch.as_tensor(u0)).max() < 1e-11
+    assert torch.abs(P.cpu() + torch.as_tensor(p0)).max() < 1e-9
+    lat.close()
+
+
+def test_hmd_step_mixed_solve():
+    dims, kappa, csw, dt = (8, 8, 8, 8), 0.125, 1.0, 0.02
+    u0 = synth.random_su3_field(dims, 0.3, 1)
+    p0 = synth.momenta(dims, 1)
+    xi = synth.heatbath_xi(dims, 1)
+    ref = O.hmd_step(torch.as_tensor(u0), torch.as_tensor(p0), torch.as_tensor(xi), dt, kappa, csw, tol=1e-13)
+    lat = Lattice(dims, kappa, csw)
+    U = to_dev(u0)
+    P = to_dev(p0)
+    lat.hmd_step(U, P, to_dev(xi), dt, prec="mixed", tol=1e-12)
+    assert max_rel(U, ref["U"]) < 1e-9
+    assert max_rel(P, ref["P"]) < 1e-9
+    lat.close()

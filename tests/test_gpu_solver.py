@@ -1,0 +1,124 @@
+"""GPU parity of the even-odd solve (FP64 and mixed precision) against the oracle.
+
+Bar (BASELINE target): relative solution error <= 1e-10 against the oracle's
+FP64 solution, both solved to tol 1e-12 (the solution error can reach
+cond(Mhat^dag Mhat) * tol); the true full-lattice residual is checked too."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_0910_0262_amd import Lattice, QCDError, capi, synth
+
+from ._gpu_helpers import make_case, rel_err, to_dev
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    ((4, 4, 4, 4), 0.3, 0.12, 1.0, 0),
+    ((10, 6, 4, 6), 0.5, 0.124, 1.0, 1),
+    ((8, 8, 16, 16), 0.5, 0.124, 1.0, 0),
+]
+IDS = ["4^4", "10x6x4x6", "8x8x16x16"]
+
+
+@pytest.fixture(scope="module", params=CASES, ids=IDS)
+def case(request):
+    dims, w, k, c, seed = request.param
+    print(f"[solve case dims={dims} width={w} kappa={k} seed={seed}]", flush=True)
+    lat, setup, u, ud = make_case(dims, w, k, c, seed)
+    b = synth.gaussian_source(dims, seed, 0)
+    ref = O.solve_full(setup, torch.as_tensor(b), 1e-13)
+    assert ref.converged
+    yield dims, lat, setup, b, ref
+    lat.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_solve_parity(case, prec):
+    dims, lat, setup, b, ref = case
+    x, st = lat.solve(to_dev(b), prec=prec, tol=1e-12)
+    print(f"  {prec}: iters={st['iters']} ru={st['reliable_updates']} true={st['true_rel_res']:.2e}", flush=True)
+    assert st["converged"] == 1
+    assert rel_err(x, ref.x) < 1e-10
+    assert st["true_rel_res"] < 1e-10
+    # the oracle's operator applied to the GPU solution
+    r = torch.as_tensor(b) - setup.M(x.cpu())
+    assert float(torch.linalg.norm(r) / torch.linalg.norm(torch.as_tensor(b))) < 1e-10
+
+
+def test_solve_deterministic(case):
+    dims, lat, setup, b, ref = case
+    x1, s1 = lat.solve(to_dev(b), prec="fp64", tol=1e-10)
+    x2, s2 = lat.solve(to_dev(b), prec="fp64", tol=1e-10)
+    assert torch.equal(x1, x2) and s1["iters"] == s2["iters"]
+    m1, _ = lat.solve(to_dev(b), prec="mixed", tol=1e-10)
+    m2, _ = lat.solve(to_dev(b), prec="mixed", tol=1e-10)
+    assert torch.equal(m1, m2)
+
+
+def test_solve_default_tolerance_meets_target(case):
+    dims, lat, setup, b, ref = case
+    for prec in ("fp64", "mixed"):
+        x, st = lat.solve(to_dev(b), prec=prec, tol=1e-10)
+        assert st["converged"] == 1 and st["normal_rel_res"] <= 1e-10
+        assert rel_err(x, ref.x) < 1e-8
+
+
+def test_enoconv_returns_last_iterate():
+    """A cap of a few iterations cannot reach tol: QCD_ENOCONV, with the last iterate and stats written."""
+    dims = (4, 4, 4, 4)
+    lat, setup, u, ud = make_case(dims, 0.3, 0.12, 1.0, 0)
+    b = to_dev(synth.gaussian_source(dims, 0, 0))
+    for prec in ("fp64", "mixed"):
+        x, st = lat.solve(b, prec=prec, tol=1e-12, max_iter=5, raise_on_noconv=False)
+        assert st["status"] == "QCD_ENOCONV" and st["converged"] == 0
+        assert 5 <= st["iters"] <= 6 and torch.isfinite(x).all()
+        assert 1e-12 < st["normal_rel_res"] < 1.0
+        with pytest.raises(QCDError) as e:
+            lat.solve(b, prec=prec, tol=1e-12, max_iter=3)
+        assert e.value.code == capi.QCD_ENOCONV
+    lat.close()
+
+
+def test_zero_mode_consistent_normal_equations():
+    """U = 1, periodic time, kappa = 1/8: the constant mode is an exact zero mode of M.
+    CG on the normal equations still converges (the right-hand side Mhat^dag bhat is
+    orthogonal to the null space), while the true residual ||b - M x|| cannot vanish."""
+    dims = (4, 4, 4, 4)
+    lat = Lattice(dims, 0.125, 1.0, t_boundary=1)
+    lat.load_gauge(to_dev(synth.unit_gauge(dims)))
+    b = to_dev(synth.gaussian_source(dims, 0, 0) + 1.0)
+    x, st = lat.solve(b, prec="fp64", tol=1e-10, max_iter=2000, raise_on_noconv=False)
+    assert st["converged"] == 1
+    assert st["true_rel_res"] > 1e-3
+    lat.close()
+
+
+def test_enan_on_nonfinite_source():
+    dims = (4, 4, 4, 4)
+    lat, setup, u, ud = make_case(dims, 0.3, 0.12, 1.0, 0)
+    b = synth.gaussian_source(dims, 0, 0)
+    b[1, 2, 3, 1, 2, 1] = np.nan
+    for prec in ("fp64", "mixed"):
+        with pytest.raises(QCDError) as e:
+            lat.solve(to_dev(b), prec=prec)
+        assert e.value.code == capi.QCD_ENAN
+    lat.close()
+
+
+def test_estate_before_load():
+    lat = Lattice((4, 4, 4, 4), 0.12, 1.0)
+    with pytest.raises(QCDError) as e:
+        lat.apply("Mhat", torch.zeros((128, 4, 3), dtype=torch.complex128, device="cuda"))
+    assert e.value.code == capi.QCD_ESTATE
+    lat.close()
+
+
+def test_zero_source():
+    dims = (4, 4, 4, 4)
+    lat, setup, u, ud = make_case(dims, 0.3, 0.12, 1.0, 0)
+    for prec in ("fp64", "mixed"):
+        x, st = lat.solve(torch.zeros((4, 4, 4, 4, 4, 3), dtype=torch.complex128, device="cuda"), prec=prec)
+        assert torch.count_nonzero(x) == 0 and st["iters"] == 0
+    lat.close()
