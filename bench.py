@@ -31,7 +31,8 @@ if ROOT not in sys.path:
 METRIC = "CG time-to-solution + M†M GB/s (% HBM peak), mixed vs FP64, 16^4 & 32^3x64"
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 FLOPS_PER_SITE = 1824.0  # 1320 hopping + 504 clover per site per M application
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k1_mixed_32x32x32x64.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k1_mixed_32x32x32x64.md")
+ROOFLINE_KERNEL = ("dslash_kernel<float, 0, true", "LinkH12", "CloverF32")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_0910_0262_amd", "csrc", f) for f in ("qcd_device.h", "dslash.hip")]
 
 
@@ -62,18 +63,62 @@ def mdagm_bytes_per_site(prec: str) -> float:
     return 2 * (k1_bytes_per_site(prec) + k2_bytes_per_site(prec))
 
 
+def _read_traffic_file():
+    with open(TRAFFIC_FILE) as f:
+        text = f.read()
+    block = text.split("```json", 1)[1].split("```", 1)[0]
+    return json.loads(block)
+
+
 def traffic_for(vh: int):
-    """HBM bytes per k1 launch from the committed rocprofv3 counter summary, if it still
-    describes the current kernel source; otherwise None."""
+    """HBM bytes per launch of the roofline kernel from the committed rocprofv3
+    counter summary, if it still describes the current kernel source; else None."""
     try:
-        with open(TRAFFIC_FILE) as f:
-            t = json.load(f)
-    except (OSError, ValueError):
+        t = _read_traffic_file()
+    except (OSError, ValueError, IndexError):
         return None
     if t.get("source_sha256") != kernel_source_hash() or t.get("vh") != vh:
         return None
-    scale = t["copy_bytes"] / ((t["copy_fetch_kib"] + t["copy_write_kib"]) * 1024.0)
-    return (t["fetch_kib"] + t["write_kib"]) * 1024.0 * scale
+    return t["traffic_bytes"]
+
+
+def traffic_summary(fetch_csv: str, write_csv: str, vh: int, command: str) -> None:
+    """Write the committed traffic summary from two rocprofv3 --pmc runs
+    (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch).  Each counter is scaled by
+    what it reads for the 2 GiB copy kernel that bench.py runs (2 GiB read,
+    2 GiB written); dispatches that returned at once (halted iterations) are
+    left out."""
+    import csv
+
+    def per_kernel(path):
+        rows = list(csv.DictReader(open(path)))
+        k = [float(r["Counter_Value"]) for r in rows if all(t in r["Kernel_Name"] for t in ROOFLINE_KERNEL)]
+        c = [float(r["Counter_Value"]) for r in rows if "stream_copy_k" in r["Kernel_Name"]]
+        med = float(np.median(k))
+        k = [v for v in k if v > 0.5 * med]
+        return float(np.mean(k)), len(k), float(np.mean(c))
+
+    f_k, n_f, f_c = per_kernel(fetch_csv)
+    w_k, n_w, w_c = per_kernel(write_csv)
+    copy_bytes = float(2 << 30)
+    fs, ws = copy_bytes / (f_c * 1024.0), copy_bytes / (w_c * 1024.0)
+    traffic = f_k * 1024.0 * fs + w_k * 1024.0 * ws
+    alg = k1_bytes_per_site("mixed") * vh
+    rec = {"kernel": " ".join(ROOFLINE_KERNEL), "vh": vh, "fetch_kib": f_k, "write_kib": w_k,
+           "dispatches": [n_f, n_w], "copy_fetch_kib": f_c, "copy_write_kib": w_c, "copy_bytes": copy_bytes,
+           "fetch_scale": fs, "write_scale": ws, "traffic_bytes": traffic, "algorithmic_bytes": alg,
+           "traffic_over_algorithmic": traffic / alg, "source_sha256": kernel_source_hash()}
+    with open(TRAFFIC_FILE, "w") as f:
+        f.write("# HBM traffic of the mixed k1 stencil at 32x32x32x64 (rocprofv3 counters)\n\n")
+        f.write("Two counter passes over the same command, run from the repository root on one MI355X:\n\n")
+        f.write("```\n" + command + "\n```\n\n")
+        f.write(f"FETCH_SIZE reads {f_c:.0f} KiB and WRITE_SIZE {w_c:.0f} KiB per dispatch of the 2 GiB copy "
+                f"kernel, so they are scaled by {fs:.3f} and {ws:.3f}.  Per launch of the k1 kernel "
+                f"({n_f} dispatches): {traffic / 1e6:.1f} MB of HBM traffic against {alg / 1e6:.1f} MB "
+                f"algorithmic ({traffic / alg:.3f}x).  `source_sha256` is the hash of the kernel sources "
+                f"the counters were taken on; bench.py reports traffic as null once they change.\n\n")
+        f.write("```json\n" + json.dumps(rec, indent=1) + "\n```\n")
+    print(json.dumps(rec))
 
 
 def cpu_baseline(dims, kappa, csw, u_np, b_np, fp64_iters: int):
@@ -110,7 +155,15 @@ def main() -> int:
     ap.add_argument("--stencil-reps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-force", action="store_true")
+    ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the committed traffic summary from two rocprofv3 --pmc counter CSVs and exit")
+    ap.add_argument("--traffic-command", type=str, default="")
     args = ap.parse_args()
+    if args.traffic_summary:
+        d = tuple(int(v) for v in args.dims.split(","))
+        traffic_summary(args.traffic_summary[0], args.traffic_summary[1], d[0] * d[1] * d[2] * d[3] // 2,
+                        args.traffic_command)
+        return 0
 
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "

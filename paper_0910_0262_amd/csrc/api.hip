@@ -88,10 +88,8 @@ struct qcd_ctx {
   double2* gint = nullptr;     // force accumulator: [mu][par][9][stride]
   double* fbuf = nullptr;      // su(3) force [V][4][8] for the HMD step
 
-  int block() const {
-    if (block_opt) return block_opt;
-    return g.Vh >= (1 << 19) ? 256 : (g.Vh >= (1 << 16) ? 128 : 64);
-  }
+  // 64-thread workgroups measured fastest for the stencils at 32^3x64
+  int block() const { return block_opt ? block_opt : 64; }
   SpF64 f64(int s) const { return SpF64{vec[s], g.stride}; }
   SpRef ref64(int s) const { return SpRef{SP_F64, vec[s], nullptr}; }
   SpRef refh(int s) const { return SpRef{SP_H, hv[s], hs[s]}; }
@@ -933,54 +931,55 @@ int qcd_hmd_step(qcd_ctx* c, double dt, void* U_dev, double* P_dev, const void* 
 int qcd_time_stencil(qcd_ctx* c, int prec, int n, double* ms) {
   QCHK(check_ctx(c));
   if (!ms) return fail(QCD_EINVAL, "null output pointer");
-  if (n < 1) return fail(QCD_EINVAL, "n must be >= 1");
+  if (n < 1 || n > 4096) return fail(QCD_EINVAL, "n must lie in [1, 4096]");
   if (prec != QCD_FP64 && prec != QCD_MIXED) return fail(QCD_EINVAL, "unknown precision");
   QCHK(need_clover(c));
-  hipEvent_t e0, e1;
-  HIPCHK(hipEventCreate(&e0));
-  if (hipEventCreate(&e1) != hipSuccess) {
-    (void)hipEventDestroy(e0);
-    return fail(QCD_EHIP, "hipEventCreate failed");
-  }
+  // n applications of Mhat^dag Mhat; an event before and after every launch
+  constexpr int kEv = 5;
+  hipEvent_t ev[kEv];
+  int made = 0;
   int rc = QCD_OK;
-  auto timed = [&](auto&& body, double* out) -> int {
-    if (hipEventRecord(e0, c->stream) != hipSuccess) return fail(QCD_EHIP, "hipEventRecord failed");
-    for (int k = 0; k < n; ++k) QCHK(body());
-    if (hipEventRecord(e1, c->stream) != hipSuccess) return fail(QCD_EHIP, "hipEventRecord failed");
-    if (hipEventSynchronize(e1) != hipSuccess) return fail(QCD_EHIP, "hipEventSynchronize failed");
-    float t = 0.f;
-    if (hipEventElapsedTime(&t, e0, e1) != hipSuccess) return fail(QCD_EHIP, "hipEventElapsedTime failed");
-    *out = double(t) / n;
-    return QCD_OK;
-  };
-  if (prec == QCD_FP64) {
-    if (rc == QCD_OK) rc = timed([&] { return k1_f64(c, V_IN_E, V_T, false, nullptr); }, &ms[0]);
-    if (rc == QCD_OK) rc = timed([&] { return k2_f64(c, V_IN_E, V_T, V_OUT_E, false, 0, 0, 0.0, false, nullptr); }, &ms[1]);
-    if (rc == QCD_OK)
-      rc = timed(
-          [&] {
-            QCHK(k1_f64(c, V_IN_E, V_T, false, nullptr));
-            QCHK(k2_f64(c, V_IN_E, V_T, V_OUT_E, false, 0, 0, 0.0, false, nullptr));
-            QCHK(k1_f64(c, V_OUT_E, V_T, true, nullptr));
-            return k2_f64(c, V_OUT_E, V_T, V_AUX, true, 0, 0, 0.0, false, nullptr);
-          },
-          &ms[2]);
-  } else {
-    if (rc == QCD_OK) rc = timed([&] { return k1_h(c, H_IN, H_T, false, nullptr); }, &ms[0]);
-    if (rc == QCD_OK) rc = timed([&] { return k2_h(c, H_IN, H_T, H_OUT, false, 0, 0, false, nullptr); }, &ms[1]);
-    if (rc == QCD_OK)
-      rc = timed(
-          [&] {
-            QCHK(k1_h(c, H_IN, H_T, false, nullptr));
-            QCHK(k2_h(c, H_IN, H_T, H_OUT, false, 0, 0, false, nullptr));
-            QCHK(k1_h(c, H_OUT, H_T, true, nullptr));
-            return k2_h(c, H_OUT, H_T, H_Q, true, 0, 0, false, nullptr);
-          },
-          &ms[2]);
+  for (; made < kEv; ++made)
+    if (hipEventCreate(&ev[made]) != hipSuccess) {
+      rc = fail(QCD_EHIP, "hipEventCreate failed");
+      break;
+    }
+  double t_k1 = 0.0, t_k2 = 0.0, t_app = 0.0;
+  for (int it = 0; it < n && rc == QCD_OK; ++it) {
+    auto rec = [&](int k) { return hipEventRecord(ev[k], c->stream) == hipSuccess ? QCD_OK : fail(QCD_EHIP, "hipEventRecord failed"); };
+    if (rc == QCD_OK) rc = rec(0);
+    if (prec == QCD_FP64) {
+      if (rc == QCD_OK) rc = k1_f64(c, V_IN_E, V_T, false, nullptr);
+      if (rc == QCD_OK) rc = rec(1);
+      if (rc == QCD_OK) rc = k2_f64(c, V_IN_E, V_T, V_OUT_E, false, 0, 0, 0.0, false, nullptr);
+      if (rc == QCD_OK) rc = rec(2);
+      if (rc == QCD_OK) rc = k1_f64(c, V_OUT_E, V_T, true, nullptr);
+      if (rc == QCD_OK) rc = rec(3);
+      if (rc == QCD_OK) rc = k2_f64(c, V_OUT_E, V_T, V_AUX, true, 0, 0, 0.0, false, nullptr);
+    } else {
+      if (rc == QCD_OK) rc = k1_h(c, H_IN, H_T, false, nullptr);
+      if (rc == QCD_OK) rc = rec(1);
+      if (rc == QCD_OK) rc = k2_h(c, H_IN, H_T, H_OUT, false, 0, 0, false, nullptr);
+      if (rc == QCD_OK) rc = rec(2);
+      if (rc == QCD_OK) rc = k1_h(c, H_OUT, H_T, true, nullptr);
+      if (rc == QCD_OK) rc = rec(3);
+      if (rc == QCD_OK) rc = k2_h(c, H_OUT, H_T, H_Q, true, 0, 0, false, nullptr);
+    }
+    if (rc == QCD_OK) rc = rec(4);
+    if (rc == QCD_OK && hipEventSynchronize(ev[4]) != hipSuccess) rc = fail(QCD_EHIP, "hipEventSynchronize failed");
+    float d[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int k = 0; k < 4 && rc == QCD_OK; ++k)
+      if (hipEventElapsedTime(&d[k], ev[k], ev[k + 1]) != hipSuccess) rc = fail(QCD_EHIP, "hipEventElapsedTime failed");
+    t_k1 += 0.5 * (d[0] + d[2]);
+    t_k2 += 0.5 * (d[1] + d[3]);
+    t_app += d[0] + d[1] + d[2] + d[3];
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  return rc;
+  for (int k = 0; k < made; ++k) (void)hipEventDestroy(ev[k]);
+  if (rc != QCD_OK) return rc;
+  ms[0] = t_k1 / n;
+  ms[1] = t_k2 / n;
+  ms[2] = t_app / n;
+  return QCD_OK;
 }
 
 int qcd_encode_half(qcd_ctx* c, int n, const void* in_dev, void* codes_dev, float* scale_dev) {

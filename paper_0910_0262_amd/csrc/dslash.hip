@@ -40,14 +40,23 @@ struct DArgs {
   double* partial;
 };
 
+// The gamma5 switch and the antiperiodic-time sign enter as multiplications
+// by +-1 rather than branches: a branch here splits the basic block and the
+// FP64 kernel then runs out of registers and spills.
 template <int MU, typename R, class A>
-__device__ __forceinline__ void hop_dir(const A& a, int i, const int x[4], Spinor<R>& acc) {
+__device__ __forceinline__ void hop_dir(const A& a, int i, const int x[4], R s5, Spinor<R>& acc) {
   const Geom& g = a.g;
   int y[4] = {x[0], x[1], x[2], x[3]};
   y[MU] = (x[MU] + 1 == g.X[MU]) ? 0 : x[MU] + 1;
   const int nf = lex(y, g) >> 1;
   y[MU] = (x[MU] == 0 ? g.X[MU] : x[MU]) - 1;
   const int nb = lex(y, g) >> 1;
+  // boundary signs of the forward and backward hop
+  R eta_f = R(1), eta_b = R(1);
+  if constexpr (MU == 3) {
+    eta_f = (g.tb < 0 && x[3] == g.X[3] - 1) ? R(-1) : R(1);
+    eta_b = (g.tb < 0 && x[3] == 0) ? R(-1) : R(1);
+  }
 
   Spinor<R> pf, pb;
   Mat<R> uf, ub;
@@ -55,30 +64,28 @@ __device__ __forceinline__ void hop_dir(const A& a, int i, const int x[4], Spino
   load_link(a.U, MU, a.par_out, i, uf);
   load(a.in, nb, pb);
   load_link(a.U, MU, 1 - a.par_out, nb, ub);
-  if (a.g5in) {
-    neg_lower(pf);
-    neg_lower(pb);
+  // gamma5 on the input: scale the lower spins by s5; the boundary sign
+  // scales the whole projected half spinor
+  const R lf = s5 * eta_f, lb = s5 * eta_b;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    pf.v[0][c] = eta_f * pf.v[0][c];
+    pf.v[1][c] = eta_f * pf.v[1][c];
+    pf.v[2][c] = lf * pf.v[2][c];
+    pf.v[3][c] = lf * pf.v[3][c];
+    pb.v[0][c] = eta_b * pb.v[0][c];
+    pb.v[1][c] = eta_b * pb.v[1][c];
+    pb.v[2][c] = lb * pb.v[2][c];
+    pb.v[3][c] = lb * pb.v[3][c];
   }
   Half<R> h, uh;
   // forward: (1 - gamma_mu) U_mu(x) psi(x + mu)
   project<MU, -1>(pf, h);
   mul_mat(uf, h, uh);
-  if (MU == 3 && g.tb < 0 && x[3] == g.X[3] - 1) {
-#pragma unroll
-    for (int k = 0; k < 2; ++k)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) uh.h[k][c] = -uh.h[k][c];
-  }
   accumulate<MU, -1>(acc, uh);
   // backward: (1 + gamma_mu) U_mu(x - mu)^dag psi(x - mu)
   project<MU, +1>(pb, h);
   mul_adj(ub, h, uh);
-  if (MU == 3 && g.tb < 0 && x[3] == 0) {
-#pragma unroll
-    for (int k = 0; k < 2; ++k)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) uh.h[k][c] = -uh.h[k][c];
-  }
   accumulate<MU, +1>(acc, uh);
 }
 
@@ -93,19 +100,23 @@ __global__ void __launch_bounds__(256) dslash_kernel(A a) {
     cb_coords(i, a.par_out, a.g, x);
     Spinor<R> acc;
     zero(acc);
-    hop_dir<0>(a, i, x, acc);
-    hop_dir<1>(a, i, x, acc);
-    hop_dir<2>(a, i, x, acc);
-    hop_dir<3>(a, i, x, acc);
-    if (a.g5out) neg_lower(acc);
-    const R c = R(a.c);
+    const R s5 = a.g5in ? R(-1) : R(1);
+    hop_dir<0>(a, i, x, s5, acc);
+    hop_dir<1>(a, i, x, s5, acc);
+    hop_dir<2>(a, i, x, s5, acc);
+    hop_dir<3>(a, i, x, s5, acc);
+    // hop scale, with gamma5 on the output folded into the lower spins
+    const R c = R(a.c), cl = a.g5out ? R(-a.c) : R(a.c);
 #pragma unroll
-    for (int s = 0; s < 4; ++s)
-#pragma unroll
-      for (int k = 0; k < 3; ++k) acc.v[s][k] = c * acc.v[s][k];
+    for (int k = 0; k < 3; ++k) {
+      acc.v[0][k] = c * acc.v[0][k];
+      acc.v[1][k] = c * acc.v[1][k];
+      acc.v[2][k] = cl * acc.v[2][k];
+      acc.v[3][k] = cl * acc.v[3][k];
+    }
     if constexpr (SITE != 0) {
       Spinor<R> sv;
-      load(a.site, i, sv);
+      load_once(a.site, i, sv);
       if constexpr (SITE == 2) apply_clover(a.cpre, i, sv);
 #pragma unroll
       for (int s = 0; s < 4; ++s)
@@ -115,7 +126,7 @@ __global__ void __launch_bounds__(256) dslash_kernel(A a) {
     if constexpr (POST) apply_clover(a.cpost, i, acc);
     if (a.epi == 2) {
       Spinor<R> yv;
-      load(a.y, i, yv);
+      load_once(a.y, i, yv);
       const R al = a.a_from_state ? R(-a.st->alpha) : R(a.a);
 #pragma unroll
       for (int s = 0; s < 4; ++s)

@@ -214,6 +214,30 @@ __device__ __forceinline__ uint2 from_h4(h4_t h) {
   return w;
 }
 
+// ------------------------------------------------------------------ streaming loads
+// Links and clover blocks are read once per kernel: load them nontemporally
+// so the caches keep the neighbour spinors, which are read up to 8 times.
+typedef double nt_d2 __attribute__((ext_vector_type(2)));
+typedef float nt_f4 __attribute__((ext_vector_type(4)));
+typedef unsigned int nt_u2 __attribute__((ext_vector_type(2)));
+typedef unsigned int nt_u4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ double2 ld_stream(const double2* p) {
+  const nt_d2 v = __builtin_nontemporal_load((const nt_d2*)p);
+  return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ float4 ld_stream(const float4* p) {
+  const nt_f4 v = __builtin_nontemporal_load((const nt_f4*)p);
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ uint2 ld_stream(const uint2* p) {
+  const nt_u2 v = __builtin_nontemporal_load((const nt_u2*)p);
+  return make_uint2(v.x, v.y);
+}
+__device__ __forceinline__ uint4 ld_stream(const uint4* p) {
+  const nt_u4 v = __builtin_nontemporal_load((const nt_u4*)p);
+  return make_uint4(v.x, v.y, v.z, v.w);
+}
+
 // ------------------------------------------------------------------ spinor fields
 // Each field is one checkerboard, structure of arrays: component chunk k of
 // site cb lives at p[k * stride + cb], so a wavefront's loads of one chunk
@@ -240,11 +264,25 @@ __device__ __forceinline__ void load(const SpF64& f, int i, Spinor<R>& v) {
     v.v[k / 3][k % 3] = {R(d.x), R(d.y)};
   }
 }
+// Output spinors are written with nontemporal stores: they are not read
+// again by the same kernel, and keeping them out of the caches leaves room
+// for the neighbour spinors.
 template <typename R>
 __device__ __forceinline__ void store(const SpF64& f, int i, const Spinor<R>& v) {
 #pragma unroll
-  for (int k = 0; k < 12; ++k)
-    f.p[(size_t)k * f.stride + i] = make_double2(double(v.v[k / 3][k % 3].re), double(v.v[k / 3][k % 3].im));
+  for (int k = 0; k < 12; ++k) {
+    const nt_d2 w = {double(v.v[k / 3][k % 3].re), double(v.v[k / 3][k % 3].im)};
+    __builtin_nontemporal_store(w, (nt_d2*)(f.p + (size_t)k * f.stride + i));
+  }
+}
+// Site-local spinor read once per kernel (the k2 site term, the epilogue's y).
+template <typename R>
+__device__ __forceinline__ void load_once(const SpF64& f, int i, Spinor<R>& v) {
+#pragma unroll
+  for (int k = 0; k < 12; ++k) {
+    const double2 d = ld_stream(f.p + (size_t)k * f.stride + i);
+    v.v[k / 3][k % 3] = {R(d.x), R(d.y)};
+  }
 }
 template <typename R>
 __device__ __forceinline__ void load(const SpF32& f, int i, Spinor<R>& v) {
@@ -302,8 +340,17 @@ __device__ __forceinline__ void store(const SpH& f, int i, const Spinor<R>& v) {
   h8_t h[3];
   const float m = encode_site(v, h);
 #pragma unroll
-  for (int k = 0; k < 3; ++k) f.p[(size_t)k * f.stride + i] = from_h8(h[k]);
-  f.s[i] = m;
+  for (int k = 0; k < 3; ++k) {
+    const uint4 w = from_h8(h[k]);
+    const nt_u4 q = {w.x, w.y, w.z, w.w};
+    __builtin_nontemporal_store(q, (nt_u4*)(f.p + (size_t)k * f.stride + i));
+  }
+  __builtin_nontemporal_store(m, f.s + i);
+}
+// binary16 site spinors are small enough to stay cache-resident: plain loads
+template <typename R>
+__device__ __forceinline__ void load_once(const SpH& f, int i, Spinor<R>& v) {
+  load(f, i, v);
 }
 
 // ------------------------------------------------------------------ link fields
@@ -332,7 +379,7 @@ __device__ __forceinline__ void load_link(const LinkF64<NC>& f, int mu, int par,
   const double2* base = f.p + (size_t)((mu * 2 + par) * NC) * f.stride + i;
 #pragma unroll
   for (int k = 0; k < NC; ++k) {
-    double2 d = base[(size_t)k * f.stride];
+    double2 d = ld_stream(base + (size_t)k * f.stride);
     u.m[k / 3][k % 3] = {R(d.x), R(d.y)};
   }
   if (NC == 6) reconstruct_row2(u);
@@ -342,7 +389,7 @@ __device__ __forceinline__ void load_link(const LinkH12& f, int mu, int par, int
   const uint2* base = f.p + (size_t)((mu * 2 + par) * 3) * f.stride + i;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    h4_t h = as_h4(base[(size_t)k * f.stride]);
+    h4_t h = as_h4(ld_stream(base + (size_t)k * f.stride));
     const int c0 = 2 * k, c1 = 2 * k + 1;  // complex entries 0..5 of rows 0, 1
     u.m[c0 / 3][c0 % 3] = {R(float(h[0])), R(float(h[1]))};
     u.m[c1 / 3][c1 % 3] = {R(float(h[2])), R(float(h[3]))};
@@ -382,13 +429,13 @@ __device__ __forceinline__ void load_block(const CloverF64& c, int i, int b, Blo
   const double2* base = c.p + (size_t)(b * 18) * c.stride + i;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    double2 d = base[(size_t)k * c.stride];
+    double2 d = ld_stream(base + (size_t)k * c.stride);
     blk.d[2 * k] = R(d.x);
     blk.d[2 * k + 1] = R(d.y);
   }
 #pragma unroll
   for (int k = 0; k < 15; ++k) {
-    double2 d = base[(size_t)(3 + k) * c.stride];
+    double2 d = ld_stream(base + (size_t)(3 + k) * c.stride);
     blk.o[k] = {R(d.x), R(d.y)};
   }
 }
@@ -397,7 +444,7 @@ __device__ __forceinline__ void load_block(const CloverF32& c, int i, int b, Blo
   float r[36];
 #pragma unroll
   for (int k = 0; k < 9; ++k) {
-    float4 d = c.p[(size_t)(b * 9 + k) * c.stride + i];
+    float4 d = ld_stream(c.p + (size_t)(b * 9 + k) * c.stride + i);
     r[4 * k] = d.x;
     r[4 * k + 1] = d.y;
     r[4 * k + 2] = d.z;
@@ -420,7 +467,7 @@ __device__ __forceinline__ void load_block(const CloverH& c, int i, int b, Block
   for (int k = 0; k < 9; ++k) {
     const int lo = 8 * k, hi = 8 * k + 8;  // half indices of this chunk
     if (hi <= 36 * b || lo >= 36 * b + 36) continue;
-    h8_t h = as_h8(c.p[(size_t)k * c.stride + i]);
+    h8_t h = as_h8(ld_stream(c.p + (size_t)k * c.stride + i));
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const int q = lo + j - 36 * b;
