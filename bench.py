@@ -32,7 +32,7 @@ METRIC = "CG time-to-solution + M†M GB/s (% HBM peak), mixed vs FP64, 16^4 & 3
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 FLOPS_PER_SITE = 1824.0  # 1320 hopping + 504 clover per site per M application
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k1_mixed_32x32x32x64.md")
-ROOFLINE_KERNEL = ("dslash_kernel<float, 0, true", "LinkH12", "CloverF32")
+ROOFLINE_KERNEL = ("dslash_kernel<float, 0, true", "LinkH12", "CloverH>")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_0910_0262_amd", "csrc", f) for f in ("qcd_device.h", "dslash.hip")]
 
 
@@ -49,18 +49,18 @@ def kernel_source_hash() -> str:
 
 
 # algorithmic bytes per even site (each field read once, neighbours counted once)
-def k1_bytes_per_site(prec: str, link_recon=12, mixed_clover=32) -> float:
+def k1_bytes_per_site(prec: str, link_recon=12, mixed_clover=16) -> float:
     if prec == "fp64":
         return 192 + 8 * (16 * (6 if link_recon == 12 else 9)) + 576 + 192
     return 52 + 8 * 24 + (288 if mixed_clover == 32 else 152) + 52
 
 
-def k2_bytes_per_site(prec: str, link_recon=12, mixed_clover=32) -> float:
+def k2_bytes_per_site(prec: str, link_recon=12, mixed_clover=16) -> float:
     return k1_bytes_per_site(prec, link_recon, mixed_clover) + (192 if prec == "fp64" else 52)
 
 
-def mdagm_bytes_per_site(prec: str) -> float:
-    return 2 * (k1_bytes_per_site(prec) + k2_bytes_per_site(prec))
+def mdagm_bytes_per_site(prec: str, mixed_clover=16) -> float:
+    return 2 * (k1_bytes_per_site(prec, mixed_clover=mixed_clover) + k2_bytes_per_site(prec, mixed_clover=mixed_clover))
 
 
 def _read_traffic_file():
@@ -144,6 +144,37 @@ def cpu_baseline(dims, kappa, csw, u_np, b_np, fp64_iters: int):
     }
 
 
+def secondary(name, dims, width, kappa, csw, tol, reps, n_apps):
+    """Smaller lattices of the paper (abstract: 8x8x16x16 and 16^4): solve times
+    and n_apps standalone Mhat^dag Mhat applications; not part of `value`."""
+    from paper_0910_0262_amd import Lattice, synth
+
+    lx, ly, lz, lt = dims
+    vh = lx * ly * lz * lt // 2
+    lat = Lattice(dims, kappa, csw)
+    lat.load_gauge(torch.as_tensor(synth.random_su3_field(dims, width, 0)).cuda())
+    b = torch.as_tensor(synth.gaussian_source(dims, 0, 0)).cuda()
+    out = {"dims": list(dims), "width": width, "kappa": kappa}
+    for prec in ("mixed", "fp64"):
+        lat.solve(b, prec=prec, tol=tol)
+        ts, its = [], []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, st = lat.solve(b, prec=prec, tol=tol)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+            its.append(st["iters"])
+        k1, k2, app = lat.time_stencil(prec, n_apps)
+        gbs = mdagm_bytes_per_site(prec) * vh / (app * 1e-3) / 1e9
+        out[prec] = {"tts_s": float(np.median(ts)), "iters": int(np.median(its)), "mdagm_ms": app,
+                     "mdagm_GB_s": gbs, "mdagm_GFLOP_s": 2 * FLOPS_PER_SITE * 2 * vh / (app * 1e-3) / 1e9,
+                     "us_per_iter": 1e6 * float(np.median(ts)) / max(1, int(np.median(its)))}
+    lat.close()
+    log(f"secondary {name}: mixed {out['mixed']['tts_s'] * 1e3:.1f} ms, fp64 {out['fp64']['tts_s'] * 1e3:.1f} ms")
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -155,6 +186,8 @@ def main() -> int:
     ap.add_argument("--stencil-reps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-force", action="store_true")
+    ap.add_argument("--no-secondary", action="store_true")
+    ap.add_argument("--mixed-clover", type=int, default=16, choices=(16, 32))
     ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the committed traffic summary from two rocprofv3 --pmc counter CSVs and exit")
     ap.add_argument("--traffic-command", type=str, default="")
@@ -192,6 +225,7 @@ def main() -> int:
     B = [torch.as_tensor(b).to(dev) for b in b_np]
     XI = torch.as_tensor(xi_np).to(dev)
     lat = Lattice(dims, kappa, csw)
+    lat.set_option(capi.QCD_OPT_MIXED_CLOVER, args.mixed_clover)
     lat.load_gauge(U)
     phi = lat.apply("Mhatdag", XI)
     torch.cuda.synchronize()
@@ -261,7 +295,8 @@ def main() -> int:
     mdagm = {}
     for p in ("mixed", "fp64"):
         k1_ms, k2_ms, app_ms = (float(v) for v in st_ms[p])
-        gbs = mdagm_bytes_per_site(p) * Vh / (app_ms * 1e-3) / 1e9
+        mc = args.mixed_clover
+        gbs = mdagm_bytes_per_site(p, mc) * Vh / (app_ms * 1e-3) / 1e9
         mdagm[p] = {
             "ms": app_ms,
             "GB_s": gbs,
@@ -270,17 +305,17 @@ def main() -> int:
             "GFLOP_s": 2 * FLOPS_PER_SITE * V / (app_ms * 1e-3) / 1e9,
             "k1_ms": k1_ms,
             "k2_ms": k2_ms,
-            "k1_GB_s": k1_bytes_per_site(p) * Vh / (k1_ms * 1e-3) / 1e9,
-            "k2_GB_s": k2_bytes_per_site(p) * Vh / (k2_ms * 1e-3) / 1e9,
+            "k1_GB_s": k1_bytes_per_site(p, mixed_clover=mc) * Vh / (k1_ms * 1e-3) / 1e9,
+            "k2_GB_s": k2_bytes_per_site(p, mixed_clover=mc) * Vh / (k2_ms * 1e-3) / 1e9,
         }
-    k1_bytes = k1_bytes_per_site("mixed") * Vh
+    k1_bytes = k1_bytes_per_site("mixed", mixed_clover=args.mixed_clover) * Vh
     k1_ms = mdagm["mixed"]["k1_ms"]
     achieved = k1_bytes / (k1_ms * 1e-3) / 1e9
-    traffic = traffic_for(Vh)
+    traffic = traffic_for(Vh) if args.mixed_clover == 16 else None
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                "kernel": "dslash_kernel<float, 0, true, ...> (mixed k1: t_o = A_oo^-1 H_oe p_e, binary16 "
-                          "spinors/links, FP32 clover)",
+                "kernel": "dslash_kernel<float, 0, true, ...CloverH> (mixed k1: t_o = A_oo^-1 H_oe p_e, binary16 "
+                          f"spinors/links, {'FP32' if args.mixed_clover == 32 else 'binary16'} clover)",
                 "bytes_per_launch": k1_bytes}
 
     out = {
@@ -317,8 +352,15 @@ def main() -> int:
         "context": "Cell/B.E. QS20 (the paper): ~10 GFLOPS and ~20 GB/s per kernel; "
                    "8.7x / 9.6x over one 2.33 GHz Xeon core (whole application)",
     }
+    out["mixed_clover_bits"] = args.mixed_clover
     lat.close()
-    del B, U, XI
+    del B, U, XI, phi
+    torch.cuda.empty_cache()
+    if not args.no_secondary:
+        out["secondary"] = {
+            "16^4": secondary("16^4", (16, 16, 16, 16), 0.3, 0.125, csw, args.tol, 5, 100),
+            "8x8x16x16": secondary("8x8x16x16", (8, 8, 16, 16), 0.5, 0.124, csw, args.tol, 5, 100),
+        }
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle Mhat^dag Mhat at the full workload")
         fp64_iters = int(round(np.mean([r["iters"] for r in rec["solves"]

@@ -82,10 +82,13 @@ typedef enum {
 typedef enum {
   QCD_OPT_LINK_RECON = 0,   /* FP64 stencil links: 12 (two rows stored, third rebuilt,
                                requires det U = 1; default) or 18 (full matrix)       */
-  QCD_OPT_MIXED_CLOVER = 1, /* clover storage in the mixed solver: 32 = FP32 (default),
-                               16 = binary16 with a per-block FP32 scale                */
-  QCD_OPT_BLOCK = 2         /* threads per workgroup of the stencil kernels (64, 128,
-                               192 or 256); 0 picks by lattice size (default)          */
+  QCD_OPT_MIXED_CLOVER = 1, /* clover storage in the mixed solver: 16 = binary16 with a
+                               per-block FP32 scale (default), 32 = FP32                */
+  QCD_OPT_BLOCK = 2,        /* threads per workgroup of the stencil kernels (64, 128,
+                               192 or 256); 0 = 64 (default)                            */
+  QCD_OPT_GRAPH = 3         /* 1: each CG iteration is replayed as a captured HIP graph;
+                               0 (default): its kernels are launched one by one (graph
+                               replay measured no faster on MI355X)                     */
 } qcd_option;
 
 /* Library version, (major << 16) | minor. */

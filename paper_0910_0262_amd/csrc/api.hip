@@ -54,7 +54,8 @@ struct qcd_ctx {
   double kappa = 0.125, csw = 1.0;
   int tb = -1;
   int link_recon = 12;
-  int mixed_clover = 32;
+  int mixed_clover = 16;
+  int use_graph = 0;
   int block_opt = 0;
   bool gauge_loaded = false;
   bool clover_ready = false;
@@ -81,7 +82,9 @@ struct qcd_ctx {
   CgState* mbox_host = nullptr;  // host-mapped ring of posted states
   CgState* mbox_dev = nullptr;   // device address of mbox_host
   hipEvent_t ev[kRing] = {};
-  int slot_ctr = 0;
+  int post_ctr = 0;             // host mirror of CgState::post_seq
+  hipStream_t cap = nullptr;    // private stream used only to capture graphs
+  hipGraphExec_t iter_graph[2] = {nullptr, nullptr};  // one CG iteration: [FP64, mixed]
   int* status = nullptr;
   int* status_host = nullptr;  // pinned
   double2* xi = nullptr;       // clover-force Xi: [par][6][9][stride]
@@ -139,6 +142,9 @@ void free_ctx(qcd_ctx* c) {
   if (c->st_host) (void)hipHostFree(c->st_host);
   if (c->status_host) (void)hipHostFree(c->status_host);
   if (c->mbox_host) (void)hipHostFree(c->mbox_host);
+  for (auto& gx : c->iter_graph)
+    if (gx) (void)hipGraphExecDestroy(gx);
+  if (c->cap) (void)hipStreamDestroy(c->cap);
   for (auto& e : c->ev)
     if (e) (void)hipEventDestroy(e);
 }
@@ -307,9 +313,10 @@ struct Pipe {
   long long seq = 0, seen = 0;
 };
 
+// slot of the next posted state; mirrors post() on the device
 int next_slot(qcd_ctx* c) {
-  const int s = c->slot_ctr;
-  c->slot_ctr = (c->slot_ctr + 1) % kRing;
+  const int s = c->post_ctr % kRing;
+  c->post_ctr = (c->post_ctr + 1) % (kRing * 1024);
   return s;
 }
 
@@ -333,7 +340,7 @@ int residual_f64(qcd_ctx* c, int x, int out_r, const CgState* st) {
 int recompute_residual(qcd_ctx* c, int restart, CgState* posted) {
   QCHK(residual_f64(c, V_X, V_R, nullptr));
   const int slot = next_slot(c);
-  HIPCHK(launch_fin_ru(c->st, c->partial, nblocks(c), restart, c->mbox_dev, slot, c->stream));
+  HIPCHK(launch_fin_ru(c->st, c->partial, nblocks(c), restart, c->mbox_dev, kRing, c->stream));
   HIPCHK(hipEventRecord(c->ev[slot], c->stream));
   if (posted) QCHK(wait_slot(c, slot, posted));
   return QCD_OK;
@@ -342,38 +349,75 @@ int recompute_residual(qcd_ctx* c, int restart, CgState* posted) {
 int init_recurrence(qcd_ctx* c, double tol, double delta, int max_iter, int mixed, CgState* posted) {
   HIPCHK(launch_norm2(c->g, c->ref64(V_RHS), c->partial, c->block(), c->stream));
   const int slot = next_slot(c);
-  HIPCHK(launch_fin_init(c->st, c->partial, nblocks(c), tol, delta, max_iter, mixed, c->mbox_dev, slot, c->stream));
+  HIPCHK(launch_fin_init(c->st, c->partial, nblocks(c), tol, delta, max_iter, mixed, c->mbox_dev, kRing, c->stream));
   HIPCHK(hipEventRecord(c->ev[slot], c->stream));
   return wait_slot(c, slot, posted);
 }
 
-int enqueue_iter_f64(qcd_ctx* c, Pipe& pp) {
-  const Geom& g = c->g;
+// The kernels of one CG iteration (they read alpha, beta and the halt flag
+// from the device state, so the sequence is the same every iteration).
+int launch_iter(qcd_ctx* c, bool mixed) {
   const int nb = nblocks(c);
-  QCHK(k1_f64(c, V_P, V_T, false, c->st));
-  QCHK(k2_f64(c, V_P, V_T, V_Q, false, 1, 0, 0.0, false, c->st));
-  HIPCHK(launch_fin_alpha(c->st, c->partial, nb, c->stream));
-  QCHK(k1_f64(c, V_Q, V_T, true, c->st));
-  QCHK(k2_f64(c, V_Q, V_T, V_R, true, 2, V_R, 0.0, true, c->st));
-  const int slot = next_slot(c);
-  HIPCHK(launch_fin_beta(c->st, c->partial, nb, c->mbox_dev, slot, c->stream));
-  HIPCHK(launch_xp_update_f64(g, c->st, c->f64(V_X), c->f64(V_P), c->f64(V_R), c->block(), c->stream));
-  HIPCHK(hipEventRecord(c->ev[slot], c->stream));
-  pp.slot[pp.seq % kRing] = slot;
-  ++pp.seq;
+  if (!mixed) {
+    QCHK(k1_f64(c, V_P, V_T, false, c->st));
+    QCHK(k2_f64(c, V_P, V_T, V_Q, false, 1, 0, 0.0, false, c->st));
+    HIPCHK(launch_fin_alpha(c->st, c->partial, nb, c->stream));
+    QCHK(k1_f64(c, V_Q, V_T, true, c->st));
+    QCHK(k2_f64(c, V_Q, V_T, V_R, true, 2, V_R, 0.0, true, c->st));
+    HIPCHK(launch_fin_beta(c->st, c->partial, nb, c->mbox_dev, kRing, c->stream));
+    HIPCHK(launch_xp_update_f64(c->g, c->st, c->f64(V_X), c->f64(V_P), c->f64(V_R), c->block(), c->stream));
+  } else {
+    QCHK(k1_h(c, H_P, H_T, false, c->st));
+    QCHK(k2_h(c, H_P, H_T, H_Q, false, 1, 0, false, c->st));
+    HIPCHK(launch_fin_alpha(c->st, c->partial, nb, c->stream));
+    QCHK(k1_h(c, H_Q, H_T, true, c->st));
+    QCHK(k2_h(c, H_Q, H_T, H_R, true, 2, H_R, true, c->st));
+    HIPCHK(launch_fin_beta(c->st, c->partial, nb, c->mbox_dev, kRing, c->stream));
+    HIPCHK(launch_xp_update_h(c->g, c->st, c->f32(), c->h(H_P), c->h(H_R), c->block(), c->stream));
+  }
   return QCD_OK;
 }
 
-int enqueue_iter_mixed(qcd_ctx* c, Pipe& pp) {
-  const int nb = nblocks(c);
-  QCHK(k1_h(c, H_P, H_T, false, c->st));
-  QCHK(k2_h(c, H_P, H_T, H_Q, false, 1, 0, false, c->st));
-  HIPCHK(launch_fin_alpha(c->st, c->partial, nb, c->stream));
-  QCHK(k1_h(c, H_Q, H_T, true, c->st));
-  QCHK(k2_h(c, H_Q, H_T, H_R, true, 2, H_R, true, c->st));
+void drop_graphs(qcd_ctx* c) {
+  for (auto& gx : c->iter_graph)
+    if (gx) {
+      (void)hipGraphExecDestroy(gx);
+      gx = nullptr;
+    }
+}
+
+// Capture one iteration on the private stream into an executable graph.
+int capture_iter(qcd_ctx* c, bool mixed) {
+  hipGraphExec_t& gx = c->iter_graph[mixed ? 1 : 0];
+  if (gx) return QCD_OK;
+  const hipStream_t saved = c->stream;
+  HIPCHK(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+  c->stream = c->cap;
+  const int rc = launch_iter(c, mixed);
+  c->stream = saved;
+  hipGraph_t graph = nullptr;
+  const hipError_t e = hipStreamEndCapture(c->cap, &graph);
+  if (rc != QCD_OK || e != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc != QCD_OK ? rc : fail(QCD_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  }
+  const hipError_t ei = hipGraphInstantiate(&gx, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (ei != hipSuccess) {
+    gx = nullptr;
+    return fail(QCD_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+  }
+  return QCD_OK;
+}
+
+int enqueue_iter(qcd_ctx* c, Pipe& pp, bool mixed) {
+  if (c->use_graph) {
+    QCHK(capture_iter(c, mixed));
+    HIPCHK(hipGraphLaunch(c->iter_graph[mixed ? 1 : 0], c->stream));
+  } else {
+    QCHK(launch_iter(c, mixed));
+  }
   const int slot = next_slot(c);
-  HIPCHK(launch_fin_beta(c->st, c->partial, nb, c->mbox_dev, slot, c->stream));
-  HIPCHK(launch_xp_update_h(c->g, c->st, c->f32(), c->h(H_P), c->h(H_R), c->block(), c->stream));
   HIPCHK(hipEventRecord(c->ev[slot], c->stream));
   pp.slot[pp.seq % kRing] = slot;
   ++pp.seq;
@@ -404,7 +448,7 @@ int cg_fp64(qcd_ctx* c, const qcd_solver_params* p, bool use_x0, CgCounters& cnt
   int restarts = 0;
   Pipe pp;
   while (!s.done) {
-    while (pp.seq - pp.seen < depth) QCHK(enqueue_iter_f64(c, pp));
+    while (pp.seq - pp.seen < depth) QCHK(enqueue_iter(c, pp, false));
     QCHK(wait_slot(c, pp.slot[pp.seen % kRing], &s));
     ++pp.seen;
     if (s.nan) return fail(QCD_ENAN, "non-finite residual in FP64 CG");
@@ -449,7 +493,7 @@ int cg_mixed(qcd_ctx* c, const qcd_solver_params* p, CgCounters& cnt) {
   int ru_seen = 0, stall = 0;
   double best_rr = s.rr_hi;
   while (!s.done) {
-    while (pp.seq - pp.seen < depth) QCHK(enqueue_iter_mixed(c, pp));
+    while (pp.seq - pp.seen < depth) QCHK(enqueue_iter(c, pp, true));
     QCHK(wait_slot(c, pp.slot[pp.seen % kRing], &s));
     const long long idx = pp.seen++;
     if (s.nan) return fail(QCD_ENAN, "non-finite residual in mixed CG");
@@ -608,6 +652,9 @@ int qcd_create(const int dims[4], int device, uintptr_t hip_stream, qcd_ctx** ou
     rc = fail(QCD_EHIP, "hipHostGetDevicePointer failed");
   for (int k = 0; k < kRing && rc == QCD_OK; ++k)
     if (hipEventCreateWithFlags(&c->ev[k], hipEventDisableTiming) != hipSuccess) rc = fail(QCD_EHIP, "hipEventCreate failed");
+  if (rc == QCD_OK && hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) != hipSuccess)
+    rc = fail(QCD_EHIP, "hipStreamCreate failed");
+  if (rc == QCD_OK && hipMemset(c->st, 0, sizeof(CgState)) != hipSuccess) rc = fail(QCD_EHIP, "hipMemset failed");
   if (rc != QCD_OK) {
     free_ctx(c);
     delete c;
@@ -638,11 +685,13 @@ int qcd_set_params(qcd_ctx* c, double kappa, double csw, int t_boundary) {
   c->tb = t_boundary;
   c->g.tb = t_boundary;
   c->clover_ready = false;
+  drop_graphs(c);
   return QCD_OK;
 }
 
 int qcd_set_option(qcd_ctx* c, int option, int value) {
   QCHK(check_ctx(c));
+  drop_graphs(c);
   switch (option) {
     case QCD_OPT_LINK_RECON:
       if (value != 12 && value != 18) return fail(QCD_EINVAL, "link reconstruction must be 12 or 18");
@@ -656,6 +705,10 @@ int qcd_set_option(qcd_ctx* c, int option, int value) {
       if (value != 0 && (value < 64 || value > 256 || value % 64 != 0))
         return fail(QCD_EINVAL, "block size must be 0 or a multiple of 64 in [64, 256]");
       c->block_opt = value;
+      return QCD_OK;
+    case QCD_OPT_GRAPH:
+      if (value != 0 && value != 1) return fail(QCD_EINVAL, "graph option must be 0 or 1");
+      c->use_graph = value;
       return QCD_OK;
     default:
       return fail(QCD_EINVAL, "unknown option");

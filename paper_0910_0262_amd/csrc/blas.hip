@@ -209,12 +209,15 @@ hipError_t launch_dot_re(const Geom& g, SpF64 a, SpF64 b, double* partial, int b
 
 // ------------------------------------------------------------------ CG scalar kernels (one workgroup)
 // Each finalisation kernel that ends an iteration posts a copy of the state
-// to mailbox[slot], host-mapped memory the host reads once the iteration's
-// event has completed.
+// to mailbox[post_seq % ring] (host-mapped memory the host reads once the
+// iteration's event has completed) and advances post_seq; the host counts
+// the posting launches it issues, so it knows the slot of each without
+// passing it as an argument (the same captured graph serves every iteration).
 __device__ __forceinline__ bool finite(double v) { return v == v && v - v == 0.0; }
 
-__device__ __forceinline__ void post(const CgState* st, CgState* mbox, int slot) {
-  if (mbox == nullptr) return;
+__device__ __forceinline__ void post(CgState* st, CgState* mbox, int ring) {
+  const int slot = st->post_seq % ring;
+  st->post_seq += 1;
   mbox[slot] = *st;
   __threadfence_system();
 }
@@ -224,7 +227,7 @@ __global__ void fin_scalar_k(CgState* st, const double* partial, int n) {
   if (threadIdx.x == 0) st->scalar = s;
 }
 __global__ void fin_init_k(CgState* st, const double* partial, int n, double tol, double delta, int max_iter,
-                           int mixed, CgState* mbox, int slot) {
+                           int mixed, CgState* mbox, int ring) {
   const double rr = block_sum_partials(partial, n);
   if (threadIdx.x != 0) return;
   st->rr = rr;
@@ -246,7 +249,7 @@ __global__ void fin_init_k(CgState* st, const double* partial, int n, double tol
   st->do_p = 0;
   st->mixed = mixed;
   st->ru_count = 0;
-  post(st, mbox, slot);
+  post(st, mbox, ring);
 }
 __global__ void fin_alpha_k(CgState* st, const double* partial, int n) {
   if (st->halt) return;
@@ -264,12 +267,12 @@ __global__ void fin_alpha_k(CgState* st, const double* partial, int n) {
 }
 // End of an iteration: |r_{k+1}|^2, beta, the stopping test (FP64) or the
 // reliable-update request (mixed; it does not stop the recurrence).
-__global__ void fin_beta_k(CgState* st, const double* partial, int n, CgState* mbox, int slot) {
+__global__ void fin_beta_k(CgState* st, const double* partial, int n, CgState* mbox, int ring) {
   if (st->halt) {
     if (threadIdx.x == 0) {
       st->do_x = 0;
       st->do_p = 0;
-      post(st, mbox, slot);
+      post(st, mbox, ring);
     }
     return;
   }
@@ -282,7 +285,7 @@ __global__ void fin_beta_k(CgState* st, const double* partial, int n, CgState* m
     st->halt = 1;
     st->do_x = 0;
     st->do_p = 0;
-    post(st, mbox, slot);
+    post(st, mbox, ring);
     return;
   }
   st->beta = rr_new / st->rr;
@@ -297,12 +300,12 @@ __global__ void fin_beta_k(CgState* st, const double* partial, int n, CgState* m
     if (rr_new <= st->stop2 || rr_new < st->delta2 * st->maxrr || st->iter >= st->max_iter) st->need_ru = 1;
     st->do_p = 1;
   }
-  post(st, mbox, slot);
+  post(st, mbox, ring);
 }
 // After an FP64 residual recomputation r = rhs - A x (partials of |r|^2):
 //   restart = 0 (reliable update): r replaces the recurrence residual, p is kept;
 //   restart = 1 (CG restart): beta = 0, so the following p update sets p = r.
-__global__ void fin_ru_k(CgState* st, const double* partial, int n, int restart, CgState* mbox, int slot) {
+__global__ void fin_ru_k(CgState* st, const double* partial, int n, int restart, CgState* mbox, int ring) {
   const double rr = block_sum_partials(partial, n);
   if (threadIdx.x != 0) return;
   st->rr_hi = rr;
@@ -314,7 +317,7 @@ __global__ void fin_ru_k(CgState* st, const double* partial, int n, int restart,
     st->done = 1;
     st->halt = 1;
     st->do_p = 0;
-    post(st, mbox, slot);
+    post(st, mbox, ring);
     return;
   }
   if (restart) st->beta = 0.0;
@@ -323,7 +326,7 @@ __global__ void fin_ru_k(CgState* st, const double* partial, int n, int restart,
   st->done = (rr <= st->stop2 || st->iter >= st->max_iter) ? 1 : 0;
   st->halt = st->done;
   st->do_p = !st->done;
-  post(st, mbox, slot);
+  post(st, mbox, ring);
 }
 
 #define FIN_LAUNCH(kernel, ...)                                     \
@@ -334,18 +337,18 @@ hipError_t launch_fin_scalar(CgState* st, const double* partial, int n, hipStrea
   FIN_LAUNCH(fin_scalar_k, st, partial, n)
 }
 hipError_t launch_fin_init(CgState* st, const double* partial, int n, double tol, double delta, int max_iter,
-                           int mixed, CgState* mbox, int slot, hipStream_t s) {
-  FIN_LAUNCH(fin_init_k, st, partial, n, tol, delta, max_iter, mixed, mbox, slot)
+                           int mixed, CgState* mbox, int ring, hipStream_t s) {
+  FIN_LAUNCH(fin_init_k, st, partial, n, tol, delta, max_iter, mixed, mbox, ring)
 }
 hipError_t launch_fin_alpha(CgState* st, const double* partial, int n, hipStream_t s) {
   FIN_LAUNCH(fin_alpha_k, st, partial, n)
 }
-hipError_t launch_fin_beta(CgState* st, const double* partial, int n, CgState* mbox, int slot, hipStream_t s) {
-  FIN_LAUNCH(fin_beta_k, st, partial, n, mbox, slot)
+hipError_t launch_fin_beta(CgState* st, const double* partial, int n, CgState* mbox, int ring, hipStream_t s) {
+  FIN_LAUNCH(fin_beta_k, st, partial, n, mbox, ring)
 }
-hipError_t launch_fin_ru(CgState* st, const double* partial, int n, int restart, CgState* mbox, int slot,
+hipError_t launch_fin_ru(CgState* st, const double* partial, int n, int restart, CgState* mbox, int ring,
                          hipStream_t s) {
-  FIN_LAUNCH(fin_ru_k, st, partial, n, restart, mbox, slot)
+  FIN_LAUNCH(fin_ru_k, st, partial, n, restart, mbox, ring)
 }
 
 // ------------------------------------------------------------------ CG vector updates

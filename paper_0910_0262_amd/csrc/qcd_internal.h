@@ -25,6 +25,7 @@ struct CgState {
   double scalar;   // generic reduction result (dot products, norms)
   int iter, max_iter;
   int halt, done, need_ru, nan, do_x, do_p, mixed, ru_count;
+  int post_seq;    // number of states posted so far; the next goes to mailbox[post_seq % ring]
 };
 
 enum SpKind { SP_NONE = 0, SP_F64 = 1, SP_F32 = 2, SP_H = 3 };
@@ -84,10 +85,10 @@ hipError_t launch_norm2(const Geom& g, SpRef x, double* partial, int block, hipS
 hipError_t launch_dot_re(const Geom& g, SpF64 a, SpF64 b, double* partial, int block, hipStream_t s);
 hipError_t launch_fin_scalar(CgState* st, const double* partial, int n, hipStream_t s);
 hipError_t launch_fin_init(CgState* st, const double* partial, int n, double tol, double delta, int max_iter,
-                           int mixed, CgState* mbox, int slot, hipStream_t s);
+                           int mixed, CgState* mbox, int ring, hipStream_t s);
 hipError_t launch_fin_alpha(CgState* st, const double* partial, int n, hipStream_t s);
-hipError_t launch_fin_beta(CgState* st, const double* partial, int n, CgState* mbox, int slot, hipStream_t s);
-hipError_t launch_fin_ru(CgState* st, const double* partial, int n, int restart, CgState* mbox, int slot,
+hipError_t launch_fin_beta(CgState* st, const double* partial, int n, CgState* mbox, int ring, hipStream_t s);
+hipError_t launch_fin_ru(CgState* st, const double* partial, int n, int restart, CgState* mbox, int ring,
                          hipStream_t s);
 hipError_t launch_xp_update_f64(const Geom& g, const CgState* st, SpF64 x, SpF64 p, SpF64 r, int block,
                                 hipStream_t s);

@@ -77,7 +77,7 @@ def test_mixed_operator_vs_oracle(case, clover_bits):
     for op, fn in [("Mhat", setup.Mhat), ("MdagM", setup.MdagM)]:
         got = lat.apply(op, to_dev(psi), prec="mixed")
         assert rel_err(got, fn(e)) < 5e-3
-    lat.set_option(capi.QCD_OPT_MIXED_CLOVER, 32)
+    lat.set_option(capi.QCD_OPT_MIXED_CLOVER, 16)
 
 
 def test_encode_half_bit_exact(case):

@@ -57,6 +57,34 @@ def test_solve_deterministic(case):
     assert torch.equal(m1, m2)
 
 
+def test_graph_replay_matches_direct_launches(case):
+    """Each CG iteration replayed from a captured HIP graph gives bit-identical
+    solutions to launching its kernels one by one; several solves in a row, with
+    other eager work (operator applications, synchronisations) in between."""
+    dims, lat, setup, b, ref = case
+    bd = to_dev(b)
+    psi = to_dev(np.ones((setup.Vh, 4, 3), complex))
+    for prec in ("fp64", "mixed"):
+        lat.set_option(capi.QCD_OPT_GRAPH, 0)
+        x0, s0 = lat.solve(bd, prec=prec, tol=1e-10)
+        lat.set_option(capi.QCD_OPT_GRAPH, 1)
+        for rep in range(3):
+            lat.apply("MdagM", psi)
+            torch.cuda.synchronize()
+            x1, s1 = lat.solve(bd, prec=prec, tol=1e-10)
+            assert torch.equal(x1, x0), (prec, rep)
+            assert s1["iters"] == s0["iters"] and s1["reliable_updates"] == s0["reliable_updates"]
+
+
+@pytest.mark.parametrize("clover_bits", [16, 32])
+def test_mixed_clover_storage_solve(case, clover_bits):
+    dims, lat, setup, b, ref = case
+    lat.set_option(capi.QCD_OPT_MIXED_CLOVER, clover_bits)
+    x, st = lat.solve(to_dev(b), prec="mixed", tol=1e-12)
+    lat.set_option(capi.QCD_OPT_MIXED_CLOVER, 16)
+    assert st["converged"] == 1 and rel_err(x, ref.x) < 1e-10
+
+
 def test_solve_default_tolerance_meets_target(case):
     dims, lat, setup, b, ref = case
     for prec in ("fp64", "mixed"):
