@@ -614,6 +614,9 @@ int qcd_create(const int dims[4], int device, uintptr_t hip_stream, qcd_ctx** ou
   g.Vh = g.V / 2;
   g.stride = g.Vh;
   g.tb = c->tb;
+  g.inv_xh = 1.0 / g.Xh;
+  g.inv_y = 1.0 / g.X[1];
+  g.inv_z = 1.0 / g.X[2];
   const size_t S = g.stride;
   int rc = QCD_OK;
   auto A = [&](auto** p, size_t bytes) {

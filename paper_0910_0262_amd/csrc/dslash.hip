@@ -40,56 +40,63 @@ struct DArgs {
   double* partial;
 };
 
-// The gamma5 switch and the antiperiodic-time sign enter as multiplications
-// by +-1 rather than branches: a branch here splits the basic block and the
-// FP64 kernel then runs out of registers and spills.
-template <int MU, typename R, class A>
-__device__ __forceinline__ void hop_dir(const A& a, int i, const int x[4], R s5, Spinor<R>& acc) {
+// One direction mu: the forward hop (1 - gamma_mu) U_mu(x) psi(x + mu) and
+// the backward hop (1 + gamma_mu) U_mu(x - mu)^dag psi(x - mu).  gamma5 on
+// the input (G5IN) is a compile-time sign that folds into the projection;
+// the antiperiodic-time sign and a binary16 field's per-site scale multiply
+// the projected half spinor once.  No branch may split this block: with a
+// branch the FP64 kernel runs out of registers and spills.
+template <int MU, bool G5IN, typename R, class A>
+__device__ __forceinline__ void hop_dir(const A& a, int i, const int x[4], Spinor<R>& acc) {
+  using SIn = decltype(a.in);
+  constexpr bool scaled = SpinorScale<SIn>::scaled;
   const Geom& g = a.g;
   int y[4] = {x[0], x[1], x[2], x[3]};
   y[MU] = (x[MU] + 1 == g.X[MU]) ? 0 : x[MU] + 1;
   const int nf = lex(y, g) >> 1;
   y[MU] = (x[MU] == 0 ? g.X[MU] : x[MU]) - 1;
   const int nb = lex(y, g) >> 1;
-  // boundary signs of the forward and backward hop
-  R eta_f = R(1), eta_b = R(1);
-  if constexpr (MU == 3) {
-    eta_f = (g.tb < 0 && x[3] == g.X[3] - 1) ? R(-1) : R(1);
-    eta_b = (g.tb < 0 && x[3] == 0) ? R(-1) : R(1);
-  }
-
   Spinor<R> pf, pb;
   Mat<R> uf, ub;
-  load(a.in, nf, pf);
+  load_raw(a.in, nf, pf);
   load_link(a.U, MU, a.par_out, i, uf);
-  load(a.in, nb, pb);
+  load_raw(a.in, nb, pb);
   load_link(a.U, MU, 1 - a.par_out, nb, ub);
-  // gamma5 on the input: scale the lower spins by s5; the boundary sign
-  // scales the whole projected half spinor
-  const R lf = s5 * eta_f, lb = s5 * eta_b;
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    pf.v[0][c] = eta_f * pf.v[0][c];
-    pf.v[1][c] = eta_f * pf.v[1][c];
-    pf.v[2][c] = lf * pf.v[2][c];
-    pf.v[3][c] = lf * pf.v[3][c];
-    pb.v[0][c] = eta_b * pb.v[0][c];
-    pb.v[1][c] = eta_b * pb.v[1][c];
-    pb.v[2][c] = lb * pb.v[2][c];
-    pb.v[3][c] = lb * pb.v[3][c];
+  if constexpr (G5IN) {
+    neg_lower(pf);
+    neg_lower(pb);
+  }
+  R sf = R(1), sb = R(1);
+  if constexpr (scaled) {
+    sf = R(scale_of(a.in, nf));
+    sb = R(scale_of(a.in, nb));
+  }
+  if constexpr (MU == 3) {
+    sf = (g.tb < 0 && x[3] == g.X[3] - 1) ? -sf : sf;
+    sb = (g.tb < 0 && x[3] == 0) ? -sb : sb;
   }
   Half<R> h, uh;
-  // forward: (1 - gamma_mu) U_mu(x) psi(x + mu)
   project<MU, -1>(pf, h);
+  if constexpr (scaled || MU == 3) {
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) h.h[k][c] = sf * h.h[k][c];
+  }
   mul_mat(uf, h, uh);
   accumulate<MU, -1>(acc, uh);
-  // backward: (1 + gamma_mu) U_mu(x - mu)^dag psi(x - mu)
   project<MU, +1>(pb, h);
+  if constexpr (scaled || MU == 3) {
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) h.h[k][c] = sb * h.h[k][c];
+  }
   mul_adj(ub, h, uh);
   accumulate<MU, +1>(acc, uh);
 }
 
-template <typename R, int SITE, bool POST, class A>
+template <typename R, int SITE, bool POST, bool G5IN, class A>
 __global__ void __launch_bounds__(256) dslash_kernel(A a) {
   if (a.st != nullptr && a.st->halt) return;  // uniform over the grid
   const int blk = xcd_block(blockIdx.x, gridDim.x);
@@ -100,11 +107,10 @@ __global__ void __launch_bounds__(256) dslash_kernel(A a) {
     cb_coords(i, a.par_out, a.g, x);
     Spinor<R> acc;
     zero(acc);
-    const R s5 = a.g5in ? R(-1) : R(1);
-    hop_dir<0>(a, i, x, s5, acc);
-    hop_dir<1>(a, i, x, s5, acc);
-    hop_dir<2>(a, i, x, s5, acc);
-    hop_dir<3>(a, i, x, s5, acc);
+    hop_dir<0, G5IN>(a, i, x, acc);
+    hop_dir<1, G5IN>(a, i, x, acc);
+    hop_dir<2, G5IN>(a, i, x, acc);
+    hop_dir<3, G5IN>(a, i, x, acc);
     // hop scale, with gamma5 on the output folded into the lower spins
     const R c = R(a.c), cl = a.g5out ? R(-a.c) : R(a.c);
 #pragma unroll
@@ -174,8 +180,9 @@ LinkF64<6> lk_of<LinkF64<6>>(const void* p, int stride) { return LinkF64<6>{(con
 template <>
 LinkH12 lk_of<LinkH12>(const void* p, int stride) { return LinkH12{(const uint2*)p, stride}; }
 
-template <typename R, class SIn, class SSite, class SOut, class LK, class CPre, class CPost, int SITE, bool POST>
-static hipError_t run(const Geom& g, const DslashOp& op, int block, hipStream_t s) {
+template <typename R, class SIn, class SSite, class SOut, class LK, class CPre, class CPost, int SITE, bool POST,
+          bool G5IN>
+static hipError_t run_g5(const Geom& g, const DslashOp& op, int block, hipStream_t s) {
   DArgs<SIn, SSite, SOut, LK, CPre, CPost> a;
   a.g = g;
   a.par_out = op.par_out;
@@ -195,8 +202,14 @@ static hipError_t run(const Geom& g, const DslashOp& op, int block, hipStream_t 
   a.st = op.st;
   a.partial = op.partial;
   const int nb = blocks_for(g.Vh, block);
-  hipLaunchKernelGGL((dslash_kernel<R, SITE, POST, decltype(a)>), dim3(nb), dim3(block), 0, s, a);
+  hipLaunchKernelGGL((dslash_kernel<R, SITE, POST, G5IN, decltype(a)>), dim3(nb), dim3(block), 0, s, a);
   return hipGetLastError();
+}
+
+template <typename R, class SIn, class SSite, class SOut, class LK, class CPre, class CPost, int SITE, bool POST>
+static hipError_t run(const Geom& g, const DslashOp& op, int block, hipStream_t s) {
+  if (op.g5in) return run_g5<R, SIn, SSite, SOut, LK, CPre, CPost, SITE, POST, true>(g, op, block, s);
+  return run_g5<R, SIn, SSite, SOut, LK, CPre, CPost, SITE, POST, false>(g, op, block, s);
 }
 
 template <int NC>

@@ -156,17 +156,34 @@ struct Geom {
   int V, Vh;
   int stride;    // element stride between components of one field (>= Vh)
   int tb;        // +1 periodic / -1 antiperiodic in time
+  double inv_xh, inv_y, inv_z;  // 1 / Xh, 1 / Ly, 1 / Lz (fast division)
 };
 
+// n / d and n % d for 0 <= n < 2^31 via the double reciprocal; the quotient
+// is off by at most one before the correction step.
+__device__ __forceinline__ int fdivmod(int n, int d, double inv, int& r) {
+  int q = int(double(n) * inv);
+  r = n - q * d;
+  if (r < 0) {
+    q -= 1;
+    r += d;
+  } else if (r >= d) {
+    q += 1;
+    r -= d;
+  }
+  return q;
+}
+
 __device__ __forceinline__ void cb_coords(int cb, int par, const Geom& g, int x[4]) {
-  int xh = cb % g.Xh;
-  int r = cb / g.Xh;
-  x[1] = r % g.X[1];
-  r /= g.X[1];
-  x[2] = r % g.X[2];
-  x[3] = r / g.X[2];
+  int xh, yy, zz;
+  int r = fdivmod(cb, g.Xh, g.inv_xh, xh);
+  r = fdivmod(r, g.X[1], g.inv_y, yy);
+  x[3] = fdivmod(r, g.X[2], g.inv_z, zz);
+  x[1] = yy;
+  x[2] = zz;
   x[0] = 2 * xh + ((x[1] + x[2] + x[3] + par) & 1);
 }
+
 __device__ __forceinline__ int lex(const int x[4], const Geom& g) {
   return x[0] + g.X[0] * (x[1] + g.X[1] * (x[2] + g.X[2] * x[3]));
 }
@@ -301,6 +318,36 @@ __device__ __forceinline__ void store(const SpF32& f, int i, const Spinor<R>& v)
     f.p[(size_t)k * f.stride + i] = make_float4(float(a.re), float(a.im), float(b.re), float(b.im));
   }
 }
+// Neighbour loads in the stencil: the components as stored, with the
+// per-site scale applied later to the projected half spinor (12 products
+// instead of 24).  FP64 fields have no scale.
+template <class F>
+struct SpinorScale {
+  static constexpr bool scaled = false;
+};
+template <>
+struct SpinorScale<SpH> {
+  static constexpr bool scaled = true;
+};
+template <typename R>
+__device__ __forceinline__ void load_raw(const SpF64& f, int i, Spinor<R>& v) {
+  load(f, i, v);
+}
+template <typename R>
+__device__ __forceinline__ void load_raw(const SpH& f, int i, Spinor<R>& v) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    h8_t h = as_h8(f.p[(size_t)k * f.stride + i]);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int c = 4 * k + j;
+      v.v[c / 3][c % 3] = {R(float(h[2 * j])), R(float(h[2 * j + 1]))};
+    }
+  }
+}
+__device__ __forceinline__ float scale_of(const SpH& f, int i) { return f.s[i]; }
+__device__ __forceinline__ float scale_of(const SpF64&, int) { return 1.0f; }
+
 template <typename R>
 __device__ __forceinline__ void load(const SpH& f, int i, Spinor<R>& v) {
   const float s = f.s[i];
@@ -455,11 +502,11 @@ __device__ __forceinline__ void load_block(const CloverF32& c, int i, int b, Blo
 #pragma unroll
   for (int k = 0; k < 15; ++k) blk.o[k] = {R(r[6 + 2 * k]), R(r[7 + 2 * k])};
 }
+// binary16 blocks are decoded without their scale; apply_clover multiplies
+// the block's product by the scale instead (6 products instead of 36).
 template <typename R>
 __device__ __forceinline__ void load_block(const CloverH& c, int i, int b, Block<R>& blk) {
   // 72 halves per site = 9 chunks; block b owns halves [36 b, 36 b + 36)
-  const float2 sc = c.s[i];
-  const float s = b == 0 ? sc.x : sc.y;
   float r[36];
 #pragma unroll
   for (int k = 0; k < 36; ++k) r[k] = 0.f;
@@ -471,7 +518,7 @@ __device__ __forceinline__ void load_block(const CloverH& c, int i, int b, Block
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const int q = lo + j - 36 * b;
-      if (q >= 0 && q < 36) r[q] = float(h[j]) * s;
+      if (q >= 0 && q < 36) r[q] = float(h[j]);
     }
   }
 #pragma unroll
@@ -479,6 +526,15 @@ __device__ __forceinline__ void load_block(const CloverH& c, int i, int b, Block
 #pragma unroll
   for (int k = 0; k < 15; ++k) blk.o[k] = {R(r[6 + 2 * k]), R(r[7 + 2 * k])};
 }
+template <class CL>
+struct CloverScale {
+  static constexpr bool scaled = false;
+};
+template <>
+struct CloverScale<CloverH> {
+  static constexpr bool scaled = true;
+};
+__device__ __forceinline__ float2 block_scales(const CloverH& c, int i) { return c.s[i]; }
 
 // v <- A v for one 6-vector (spins 2b, 2b+1)
 template <typename R>
@@ -500,6 +556,8 @@ __device__ __forceinline__ void block_mv(const Block<R>& a, Cx<R> v[6]) {
 
 template <typename R, class CL>
 __device__ __forceinline__ void apply_clover(const CL& c, int i, Spinor<R>& s) {
+  float2 sc = make_float2(1.f, 1.f);
+  if constexpr (CloverScale<CL>::scaled) sc = block_scales(c, i);
 #pragma unroll
   for (int b = 0; b < 2; ++b) {
     Block<R> blk;
@@ -508,8 +566,9 @@ __device__ __forceinline__ void apply_clover(const CL& c, int i, Spinor<R>& s) {
 #pragma unroll
     for (int k = 0; k < 6; ++k) v[k] = s.v[2 * b + k / 3][k % 3];
     block_mv(blk, v);
+    const R f = R(b == 0 ? sc.x : sc.y);
 #pragma unroll
-    for (int k = 0; k < 6; ++k) s.v[2 * b + k / 3][k % 3] = v[k];
+    for (int k = 0; k < 6; ++k) s.v[2 * b + k / 3][k % 3] = CloverScale<CL>::scaled ? f * v[k] : v[k];
   }
 }
 
