@@ -32,7 +32,7 @@ METRIC = "CG time-to-solution + M†M GB/s (% HBM peak), mixed vs FP64, 16^4 & 3
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 FLOPS_PER_SITE = 1824.0  # 1320 hopping + 504 clover per site per M application
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k1_mixed_32x32x32x64.md")
-ROOFLINE_KERNEL = ("dslash_kernel<float, 0, true", "LinkH12", "CloverH>")
+ROOFLINE_KERNEL = ("dslash_kernel<float, 0, true, false,", "LinkH12", "CloverH>")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_0910_0262_amd", "csrc", f) for f in ("qcd_device.h", "dslash.hip")]
 
 
@@ -314,7 +314,7 @@ def main() -> int:
     traffic = traffic_for(Vh) if args.mixed_clover == 16 else None
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                "kernel": "dslash_kernel<float, 0, true, ...CloverH> (mixed k1: t_o = A_oo^-1 H_oe p_e, binary16 "
+                "kernel": "dslash_kernel<float, 0, true, false, ...CloverH> (mixed k1: t_o = A_oo^-1 H_oe p_e, binary16 "
                           f"spinors/links, {'FP32' if args.mixed_clover == 32 else 'binary16'} clover)",
                 "bytes_per_launch": k1_bytes}
 

@@ -1026,8 +1026,8 @@ int qcd_time_stencil(qcd_ctx* c, int prec, int n, double* ms) {
     float d[4] = {0.f, 0.f, 0.f, 0.f};
     for (int k = 0; k < 4 && rc == QCD_OK; ++k)
       if (hipEventElapsedTime(&d[k], ev[k], ev[k + 1]) != hipSuccess) rc = fail(QCD_EHIP, "hipEventElapsedTime failed");
-    t_k1 += 0.5 * (d[0] + d[2]);
-    t_k2 += 0.5 * (d[1] + d[3]);
+    t_k1 += d[0];
+    t_k2 += d[1];
     t_app += d[0] + d[1] + d[2] + d[3];
   }
   for (int k = 0; k < made; ++k) (void)hipEventDestroy(ev[k]);
