@@ -77,6 +77,7 @@ struct qcd_ctx {
   float4* x32 = nullptr;
   double* partial = nullptr;
   int n_partial = 0;
+
   CgState* st = nullptr;
   CgState* st_host = nullptr;  // pinned
   CgState* mbox_host = nullptr;  // host-mapped ring of posted states
@@ -134,6 +135,7 @@ void free_ctx(qcd_ctx* c) {
   for (auto* p : c->hs) f(p);
   f(c->x32);
   f(c->partial);
+
   f(c->st);
   f(c->status);
   f(c->xi);
@@ -358,6 +360,10 @@ int init_recurrence(qcd_ctx* c, double tol, double delta, int max_iter, int mixe
 // from the device state, so the sequence is the same every iteration).
 int launch_iter(qcd_ctx* c, bool mixed) {
   const int nb = nblocks(c);
+  // The reductions are finished by one-workgroup kernels.  (Finishing them
+  // inside the stencil kernels with a last-workgroup-arrives scheme needs a
+  // device-scope fence per workgroup, which writes back the XCD's L2 on this
+  // GPU and made the iteration three times slower.)
   if (!mixed) {
     QCHK(k1_f64(c, V_P, V_T, false, c->st));
     QCHK(k2_f64(c, V_P, V_T, V_Q, false, 1, 0, 0.0, false, c->st));
@@ -641,6 +647,7 @@ int qcd_create(const int dims[4], int device, uintptr_t hip_stream, qcd_ctx** ou
   A(&c->x32, 6 * S * sizeof(float4));
   c->n_partial = g.Vh / 64 + 64;
   A(&c->partial, (size_t)c->n_partial * sizeof(double));
+
   A(&c->st, sizeof(CgState));
   A(&c->status, sizeof(int));
   if (rc == QCD_OK && hipHostMalloc((void**)&c->st_host, sizeof(CgState), hipHostMallocDefault) != hipSuccess)

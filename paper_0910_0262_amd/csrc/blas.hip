@@ -213,15 +213,6 @@ hipError_t launch_dot_re(const Geom& g, SpF64 a, SpF64 b, double* partial, int b
 // iteration's event has completed) and advances post_seq; the host counts
 // the posting launches it issues, so it knows the slot of each without
 // passing it as an argument (the same captured graph serves every iteration).
-__device__ __forceinline__ bool finite(double v) { return v == v && v - v == 0.0; }
-
-__device__ __forceinline__ void post(CgState* st, CgState* mbox, int ring) {
-  const int slot = st->post_seq % ring;
-  st->post_seq += 1;
-  mbox[slot] = *st;
-  __threadfence_system();
-}
-
 __global__ void fin_scalar_k(CgState* st, const double* partial, int n) {
   const double s = block_sum_partials(partial, n);
   if (threadIdx.x == 0) st->scalar = s;
@@ -254,53 +245,15 @@ __global__ void fin_init_k(CgState* st, const double* partial, int n, double tol
 __global__ void fin_alpha_k(CgState* st, const double* partial, int n) {
   if (st->halt) return;
   const double qq = block_sum_partials(partial, n);
-  if (threadIdx.x != 0) return;
-  st->qq = qq;
-  if (!(qq > 0.0) || !finite(qq)) {
-    st->nan = 1;
-    st->done = 1;
-    st->halt = 1;
-    st->alpha = 0.0;
-    return;
-  }
-  st->alpha = st->rr / qq;
+  if (threadIdx.x == 0) state_alpha(st, qq);
 }
-// End of an iteration: |r_{k+1}|^2, beta, the stopping test (FP64) or the
-// reliable-update request (mixed; it does not stop the recurrence).
 __global__ void fin_beta_k(CgState* st, const double* partial, int n, CgState* mbox, int ring) {
   if (st->halt) {
-    if (threadIdx.x == 0) {
-      st->do_x = 0;
-      st->do_p = 0;
-      post(st, mbox, ring);
-    }
+    if (threadIdx.x == 0) state_halted(st, mbox, ring);
     return;
   }
   const double rr_new = block_sum_partials(partial, n);
-  if (threadIdx.x != 0) return;
-  st->iter += 1;
-  if (!finite(rr_new)) {
-    st->nan = 1;
-    st->done = 1;
-    st->halt = 1;
-    st->do_x = 0;
-    st->do_p = 0;
-    post(st, mbox, ring);
-    return;
-  }
-  st->beta = rr_new / st->rr;
-  st->rr = rr_new;
-  st->do_x = 1;
-  if (!st->mixed) {
-    st->done = (rr_new <= st->stop2 || st->iter >= st->max_iter) ? 1 : 0;
-    st->halt = st->done;
-    st->do_p = !st->done;
-  } else {
-    if (rr_new > st->maxrr) st->maxrr = rr_new;
-    if (rr_new <= st->stop2 || rr_new < st->delta2 * st->maxrr || st->iter >= st->max_iter) st->need_ru = 1;
-    st->do_p = 1;
-  }
-  post(st, mbox, ring);
+  if (threadIdx.x == 0) state_beta(st, rr_new, mbox, ring);
 }
 // After an FP64 residual recomputation r = rhs - A x (partials of |r|^2):
 //   restart = 0 (reliable update): r replaces the recurrence residual, p is kept;

@@ -28,6 +28,69 @@ struct CgState {
   int post_seq;    // number of states posted so far; the next goes to mailbox[post_seq % ring]
 };
 
+// ---- CG state updates, shared by the one-workgroup finalisation kernels and
+// the stencil kernels that finish their own reduction (one thread runs them).
+__device__ __forceinline__ bool finite(double v) { return v == v && v - v == 0.0; }
+
+// Copy the state to mailbox[post_seq % ring] (host-mapped memory the host
+// reads once the iteration's event has completed) and advance post_seq; the
+// host counts the posting launches it issues, so it knows each slot.
+__device__ __forceinline__ void post(CgState* st, CgState* mbox, int ring) {
+  const int slot = st->post_seq % ring;
+  st->post_seq = (st->post_seq + 1) % (ring * 1024);
+  mbox[slot] = *st;
+  __threadfence_system();
+}
+
+// alpha = |r|^2 / |Mhat p|^2
+__device__ __forceinline__ void state_alpha(CgState* st, double qq) {
+  st->qq = qq;
+  if (!(qq > 0.0) || !finite(qq)) {
+    st->nan = 1;
+    st->done = 1;
+    st->halt = 1;
+    st->alpha = 0.0;
+    return;
+  }
+  st->alpha = st->rr / qq;
+}
+
+// End of an iteration: |r_{k+1}|^2, beta, the stopping test (FP64) or the
+// reliable-update request (mixed; it does not stop the recurrence).  Posts.
+__device__ __forceinline__ void state_beta(CgState* st, double rr_new, CgState* mbox, int ring) {
+  st->iter += 1;
+  if (!finite(rr_new)) {
+    st->nan = 1;
+    st->done = 1;
+    st->halt = 1;
+    st->do_x = 0;
+    st->do_p = 0;
+    post(st, mbox, ring);
+    return;
+  }
+  st->beta = rr_new / st->rr;
+  st->rr = rr_new;
+  st->do_x = 1;
+  if (!st->mixed) {
+    st->done = (rr_new <= st->stop2 || st->iter >= st->max_iter) ? 1 : 0;
+    st->halt = st->done;
+    st->do_p = !st->done;
+  } else {
+    if (rr_new > st->maxrr) st->maxrr = rr_new;
+    if (rr_new <= st->stop2 || rr_new < st->delta2 * st->maxrr || st->iter >= st->max_iter) st->need_ru = 1;
+    st->do_p = 1;
+  }
+  post(st, mbox, ring);
+}
+
+// The iteration was already stopped: nothing to update, but the host still
+// expects one posted state per iteration.
+__device__ __forceinline__ void state_halted(CgState* st, CgState* mbox, int ring) {
+  st->do_x = 0;
+  st->do_p = 0;
+  post(st, mbox, ring);
+}
+
 enum SpKind { SP_NONE = 0, SP_F64 = 1, SP_F32 = 2, SP_H = 3 };
 struct SpRef {
   int kind;
