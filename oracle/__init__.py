@@ -39,3 +39,4 @@ from .solve import cg, solve_full, dense_matrix  # noqa: F401
 from .force import action, action_and_gradient, project_force, action_variational  # noqa: F401
 from .hmd import expi_su3, hmd_step, hamiltonian  # noqa: F401
 from .quant import quantize16, dequantize16, link_to_half12, reconstruct12  # noqa: F401
+from . import md  # noqa: F401

@@ -1,0 +1,248 @@
+"""Pins of the oracle's gauge action, clover determinant, their forces, the
+R-algorithm trajectory and reunitarisation.
+
+* Wilson gauge action: zero on unit and pure-gauge fields; the closed form
+  beta V (2/3)(1 - cos B) of a constant abelian flux B; an explicit
+  coordinate-loop sum over plaquettes on a small lattice; gauge invariance.
+* Clover determinant: the closed form -8 Vh ln(1 - (kappa c_sw sin B)^2) of
+  the flux field; gauge invariance; stationary at pure gauge.
+* Forces: central finite differences along su(3) generators.
+* Two-flavour identity: summing the pseudofermion force over a complete set
+  of noise vectors (E[xi xi^dag] = 1) and adding the determinant force gives
+  the force of -ln det(M^dag M) of the dense unpreconditioned operator.
+* Leapfrog with phi fixed: energy violation over a fixed trajectory length
+  falls as dt^2; exact reversibility.
+* Reunitarisation: output in SU(3); identity on SU(3) input; row 0 direction kept.
+"""
+import itertools
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from oracle import md
+from oracle.solve import dense_full_operator
+from paper_0910_0262_amd import synth
+
+C = torch.complex128
+EYE = torch.eye(3, dtype=C)
+
+
+def _dag(m):
+    return m.conj().transpose(-1, -2)
+
+
+# ---------------------------------------------------------------- gauge action
+def test_gauge_action_unit_and_pure_gauge():
+    dims = (4, 4, 2, 4)
+    assert float(md.gauge_action(torch.as_tensor(synth.unit_gauge(dims)), 5.7)) == 0.0
+    pg = torch.as_tensor(synth.pure_gauge(dims, 3))
+    assert abs(float(md.gauge_action(pg, 5.7))) < 1e-11
+
+
+@pytest.mark.parametrize("n", [1, 3])
+def test_gauge_action_abelian_flux_closed_form(n):
+    dims = (4, 6, 2, 2)
+    lx, ly, lz, lt = dims
+    b = 2 * np.pi * n / (lx * ly)
+    u = torch.as_tensor(synth.abelian_flux_field(dims, n))
+    beta = 6.0
+    expect = beta * lx * ly * lz * lt * (2.0 / 3.0) * (1.0 - np.cos(b))
+    assert abs(float(md.gauge_action(u, beta)) - expect) < 1e-11 * max(1.0, expect)
+
+
+def test_gauge_action_coordinate_loop():
+    """Plaquettes by explicit coordinate arithmetic, site by site."""
+    dims = (2, 4, 2, 4)
+    lx, ly, lz, lt = dims
+    u = synth.random_su3_field(dims, 0.4, 5)
+    ext = (lx, ly, lz, lt)
+
+    def link(c, mu):
+        x, y, z, t = (c[i] % ext[i] for i in range(4))
+        return u[t, z, y, x, mu]
+
+    def step(c, mu):
+        d = list(c)
+        d[mu] += 1
+        return d
+
+    tot = 0.0
+    for c in itertools.product(range(lx), range(ly), range(lz), range(lt)):
+        for mu in range(4):
+            for nu in range(mu + 1, 4):
+                p = link(c, mu) @ link(step(c, mu), nu) @ link(step(c, nu), mu).conj().T @ link(c, nu).conj().T
+                tot += 1.0 - np.trace(p).real / 3.0
+    assert abs(float(md.gauge_action(torch.as_tensor(u), 5.5)) - 5.5 * tot) < 1e-11 * 5.5 * tot
+
+
+def test_gauge_action_gauge_invariant():
+    dims = (4, 2, 4, 2)
+    u = torch.as_tensor(synth.random_su3_field(dims, 0.5, 2))
+    om = synth.random_su3_sites(dims, 9, 0.7)
+    ut = torch.as_tensor(synth.gauge_transform(u.numpy(), om))
+    a, b = float(md.gauge_action(u, 5.5)), float(md.gauge_action(ut, 5.5))
+    assert abs(a - b) < 1e-12 * abs(a)
+
+
+# ---------------------------------------------------------------- clover determinant
+@pytest.mark.parametrize("n", [1, 2])
+def test_clover_det_abelian_flux_closed_form(n):
+    dims = (4, 4, 2, 2)
+    lx, ly, lz, lt = dims
+    kappa, csw = 0.13, 1.3
+    b = 2 * np.pi * n / (lx * ly)
+    u = torch.as_tensor(synth.abelian_flux_field(dims, n))
+    vh = lx * ly * lz * lt // 2
+    a = kappa * csw * np.sin(b)
+    expect = -2.0 * vh * 4.0 * np.log(1.0 - a * a)
+    got = float(md.clover_det_action(u, kappa, csw))
+    assert abs(got - expect) < 1e-11 * abs(expect), (got, expect)
+
+
+def test_clover_det_gauge_invariant_and_pure_gauge():
+    dims = (4, 2, 2, 4)
+    u = torch.as_tensor(synth.random_su3_field(dims, 0.5, 4))
+    om = synth.random_su3_sites(dims, 8, 0.7)
+    ut = torch.as_tensor(synth.gauge_transform(u.numpy(), om))
+    a, b = float(md.clover_det_action(u, 0.125, 1.0)), float(md.clover_det_action(ut, 0.125, 1.0))
+    assert abs(a - b) < 1e-12 * abs(a)
+    pg = torch.as_tensor(synth.pure_gauge(dims, 1))
+    assert abs(float(md.clover_det_action(pg, 0.125, 1.0))) < 1e-12
+    g = md.gradient(lambda v: md.clover_det_action(v, 0.125, 1.0), pg)
+    assert float(torch.abs(O.project_force(pg, g)).max()) < 1e-12
+
+
+# ---------------------------------------------------------------- forces vs finite differences
+def _fd_force(action, u, site, mu, a, eps=1e-5):
+    lam = O.gell_mann()
+    vals = []
+    for sgn in (+1, -1):
+        up = u.clone()
+        up[site + (mu,)] = torch.linalg.matrix_exp(1j * sgn * eps * lam[a] / 2) @ u[site + (mu,)]
+        vals.append(float(action(up)))
+    return (vals[0] - vals[1]) / (2 * eps)
+
+
+PICKS = [((0, 0, 0, 0), 0, 0), ((1, 1, 0, 2), 3, 4), ((3, 0, 1, 1), 1, 7), ((2, 1, 1, 3), 2, 2), ((1, 0, 1, 0), 3, 5)]
+
+
+@pytest.mark.parametrize("which", ["gauge", "det"])
+def test_force_vs_fd(which):
+    dims = (4, 2, 2, 4)
+    u = torch.as_tensor(synth.random_su3_field(dims, 0.4, 6))
+    if which == "gauge":
+        act = lambda v: md.gauge_action(v, 5.6)  # noqa: E731
+    else:
+        act = lambda v: md.clover_det_action(v, 0.125, 1.0)  # noqa: E731
+    f = O.project_force(u, md.gradient(act, u))
+    scale = float(torch.abs(f).max())
+    assert scale > 1e-3
+    for site, mu, a in PICKS:
+        fd = _fd_force(act, u, site, mu, a)
+        assert abs(fd - float(f[site + (mu, a)])) < 1e-8 * max(1.0, scale), (which, site, mu, a, fd)
+
+
+@pytest.mark.slow
+def test_two_flavour_identity_full_determinant():
+    """sum over a complete noise basis of the pseudofermion force, plus the
+    determinant force, equals the force of -ln det(M^dag M) = -2 ln|det M|."""
+    dims = (2, 2, 2, 4)
+    kappa, csw = 0.12, 1.0
+    lx, ly, lz, lt = dims
+    u = torch.as_tensor(synth.random_su3_field(dims, 0.35, 3))
+    vh = lx * ly * lz * lt // 2
+    setup = O.CloverSetup(u, kappa, csw)
+    g_sum = torch.zeros_like(u)
+    for k in range(vh * 12):
+        xi = torch.zeros(vh * 12, dtype=C)
+        xi[k] = 1.0
+        phi = setup.Mhat_dag(xi.reshape(vh, 4, 3))
+        _, g, _, _ = O.action_and_gradient(u, kappa, csw, phi, tol=1e-14)
+        g_sum = g_sum + g
+    g_sum = g_sum + md.gradient(lambda v: md.clover_det_action(v, kappa, csw), u)
+
+    def full(v):
+        m = dense_full_operator(O.CloverSetup(v, kappa, csw), "M")
+        return -2.0 * torch.linalg.slogdet(m)[1]
+
+    g_ref = md.gradient(full, u)
+    f_sum, f_ref = O.project_force(u, g_sum), O.project_force(u, g_ref)
+    assert float(torch.abs(f_sum - f_ref).max()) < 1e-9 * float(torch.abs(f_ref).max())
+    # the pseudofermion part alone misses the determinant force
+    f_pf = O.project_force(u, g_sum - md.gradient(lambda v: md.clover_det_action(v, kappa, csw), u))
+    assert float(torch.abs(f_pf - f_ref).max()) > 1e-3 * float(torch.abs(f_ref).max())
+
+
+# ---------------------------------------------------------------- leapfrog
+DIMS = (4, 2, 2, 4)
+KAPPA, CSW, BETA = 0.12, 1.0, 5.6
+
+
+@pytest.mark.slow
+def test_full_leapfrog_energy_violation_dt_squared():
+    u0 = torch.as_tensor(synth.random_su3_field(DIMS, 0.3, 11))
+    p0 = torch.as_tensor(synth.momenta(DIMS, 11))
+    phi = O.CloverSetup(u0, KAPPA, CSW).Mhat_dag(torch.as_tensor(synth.heatbath_xi(DIMS, 11)))
+    h0 = md.hamiltonian_fixed_phi(u0, p0, phi, KAPPA, CSW, BETA)
+    tau = 0.08
+    dh = []
+    for n in (2, 4):
+        u1, p1 = md.leapfrog_fixed_phi(u0, p0, phi, tau / n, n, KAPPA, CSW, BETA)
+        dh.append(abs(md.hamiltonian_fixed_phi(u1, p1, phi, KAPPA, CSW, BETA) - h0))
+    ratio = dh[0] / dh[1]
+    assert 3.3 < ratio < 4.8, (dh, ratio)
+
+
+@pytest.mark.slow
+def test_full_leapfrog_reversible():
+    u0 = torch.as_tensor(synth.random_su3_field(DIMS, 0.3, 12))
+    p0 = torch.as_tensor(synth.momenta(DIMS, 12))
+    phi = O.CloverSetup(u0, KAPPA, CSW).Mhat_dag(torch.as_tensor(synth.heatbath_xi(DIMS, 12)))
+    u1, p1 = md.leapfrog_fixed_phi(u0, p0, phi, 0.03, 3, KAPPA, CSW, BETA)
+    u2, p2 = md.leapfrog_fixed_phi(u1, -p1, phi, 0.03, 3, KAPPA, CSW, BETA)
+    assert float(torch.abs(u2 - u0).max()) < 1e-12
+    assert float(torch.abs(p2 + p0).max()) < 1e-9
+
+
+def test_trajectory_two_flavours_matches_single_steps():
+    """At N_f = 2 without gauge or determinant terms a trajectory is a chain of HMD steps."""
+    u0 = torch.as_tensor(synth.random_su3_field(DIMS, 0.3, 13))
+    p0 = torch.as_tensor(synth.momenta(DIMS, 13))
+    xis = [torch.as_tensor(synth.heatbath_xi(DIMS, 13 + k)) for k in range(2)]
+    u, p, _ = md.trajectory(u0, p0, xis, 0.02, KAPPA, CSW, 0.0, with_det=False, n_f=2.0)
+    uu, pp = u0, p0
+    for xi in xis:
+        st = O.hmd_step(uu, pp, xi, 0.02, KAPPA, CSW)
+        uu, pp = st["U"], st["P"]
+    assert float(torch.abs(u - uu).max()) < 1e-13
+    assert float(torch.abs(p - pp).max()) < 1e-11
+
+
+def test_trajectory_flavour_weight():
+    """N_f scales the fermion and determinant forces; with both refresh points
+    coinciding (dt -> tiny), the momentum change is (N_f/2) times the N_f = 2 one."""
+    u0 = torch.as_tensor(synth.random_su3_field(DIMS, 0.3, 14))
+    p0 = torch.zeros(DIMS[::-1] + (4, 8), dtype=torch.float64)
+    xi = [torch.as_tensor(synth.heatbath_xi(DIMS, 14))]
+    dt = 1e-7
+    _, p2, _ = md.trajectory(u0, p0, xi, dt, KAPPA, CSW, 0.0, n_f=2.0)
+    _, p1, _ = md.trajectory(u0, p0, xi, dt, KAPPA, CSW, 0.0, n_f=1.0)
+    assert float(torch.abs(p1 - 0.5 * p2).max()) < 1e-6 * float(torch.abs(p2).max())
+
+
+# ---------------------------------------------------------------- reunitarisation
+def test_reunitarize():
+    dims = (2, 2, 2, 2)
+    u = torch.as_tensor(synth.random_su3_field(dims, 0.5, 1))
+    assert float(torch.abs(md.reunitarize(u) - u).max()) < 1e-14
+    rng = np.random.default_rng(3)
+    noise = torch.as_tensor(rng.standard_normal(u.shape) + 1j * rng.standard_normal(u.shape)) * 1e-3
+    w = md.reunitarize(u + noise)
+    assert float(torch.abs(_dag(w) @ w - EYE).max()) < 1e-14
+    assert float(torch.abs(torch.linalg.det(w) - 1).max()) < 1e-14
+    assert float(torch.abs(w - u).max()) < 1e-2
+    r0 = (u + noise)[..., 0, :]
+    cosang = torch.abs((r0.conj() * w[..., 0, :]).sum(-1)) / torch.linalg.norm(r0, dim=-1)
+    assert float(torch.abs(cosang - 1).max()) < 1e-14

@@ -104,3 +104,57 @@ def test_wrong_force_sign_fails_fd(monkeypatch):
     u = torch.as_tensor(synth.random_su3_field(tf.DIMS, 0.3, 0))
     with pytest.raises(AssertionError):
         tf.test_force_vs_fd_generators(u, 1.0)
+
+
+# ---------------------------------------------------------------- gauge action, determinant, reunitarisation
+from oracle import md  # noqa: E402
+
+from . import test_oracle_md as tm  # noqa: E402
+
+
+def test_open_plaquette_fails_coordinate_loop(monkeypatch):
+    def bad_plaquettes(u):
+        out = {}
+        for mu in range(4):
+            for nu in range(mu + 1, 4):
+                um, un = u[..., mu, :, :], u[..., nu, :, :]
+                # U_nu taken at x - mu instead of x + mu
+                out[(mu, nu)] = um @ md._sh(un, mu, -1) @ md._sh(um, nu, 1).conj().transpose(-1, -2) @ \
+                    un.conj().transpose(-1, -2)
+        return out
+
+    monkeypatch.setattr(md, "plaquettes", bad_plaquettes)
+    with pytest.raises(AssertionError):
+        tm.test_gauge_action_coordinate_loop()
+
+
+def test_one_flavour_determinant_fails_flux_closed_form(monkeypatch):
+    orig = md.clover_det_action
+    monkeypatch.setattr(md, "clover_det_action", lambda u, k, c: 0.5 * orig(u, k, c))
+    with pytest.raises(AssertionError):
+        tm.test_clover_det_abelian_flux_closed_form(1)
+
+
+@pytest.mark.slow
+def test_even_site_determinant_fails_two_flavour_identity(monkeypatch):
+    def det_even(u, kappa, csw):
+        lt, lz, ly, lx = u.shape[:4]
+        a = core.clover_matrix(u, kappa, csw).reshape(-1, 12, 12)
+        ev, _ = core.eo_index((lx, ly, lz, lt))
+        return -2.0 * torch.linalg.slogdet(a[ev])[1].sum()
+
+    monkeypatch.setattr(md, "clover_det_action", det_even)
+    with pytest.raises(AssertionError):
+        tm.test_two_flavour_identity_full_determinant()
+
+
+def test_reunitarize_without_conjugate_fails(monkeypatch):
+    def bad(u):
+        a = u[..., 0, :] / torch.linalg.norm(u[..., 0, :], dim=-1, keepdim=True)
+        b = u[..., 1, :] - (a.conj() * u[..., 1, :]).sum(-1, keepdim=True) * a
+        b = b / torch.linalg.norm(b, dim=-1, keepdim=True)
+        return torch.stack([a, b, torch.linalg.cross(a, b)], dim=-2)
+
+    monkeypatch.setattr(md, "reunitarize", bad)
+    with pytest.raises(AssertionError):
+        tm.test_reunitarize()
