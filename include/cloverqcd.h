@@ -40,7 +40,7 @@
  *
  * Streams: all device work is enqueued on the stream given to qcd_create.
  * qcd_apply and the load calls are stream-ordered and return without waiting.
- * qcd_solve, qcd_action_force and qcd_hmd_step wait for their work before
+ * qcd_solve, qcd_action_force, qcd_hmd_step and the calls below them wait for their work before
  * returning, because they return host-visible results.
  *
  * Errors: every call returns a qcd_status.  Arguments are validated before
@@ -193,6 +193,60 @@ int qcd_action_force(qcd_ctx *ctx, const qcd_solver_params *params, const void *
  * action at U_1/2; stats (may be NULL) the inner solve's stats. */
 int qcd_hmd_step(qcd_ctx *ctx, double dt, void *U_dev, double *P_dev, const void *xi_dev,
                  const qcd_solver_params *params, double *S, qcd_solver_stats *stats);
+
+/* Wilson gauge action on the loaded gauge field,
+ *   S_g = beta sum_{x, mu<nu} (1 - Re tr U_mu,nu(x) / 3),
+ *   U_mu,nu(x) = U_mu(x) U_nu(x + mu) U_mu(x + nu)^dag U_nu(x)^dag,
+ * and its derivative in the conventions of qcd_action_force: G_dev
+ * (complex128 [V][4][3][3]) and F_dev (float64 [V][4][8]), each may be NULL;
+ * S may be NULL.  The R-algorithm application of the paper evolves the gauge
+ * field under gauge and fermion forces together (section 1); the paper
+ * prints no gauge action, so this is the standard plaquette action.  Waits
+ * for its work.  QCD_ESTATE without a gauge field, QCD_EINVAL for a
+ * non-finite beta. */
+int qcd_gauge_action_force(qcd_ctx *ctx, double beta, double *S, void *G_dev, double *F_dev);
+
+/* Clover determinant on odd sites, S_det = -2 sum_{x odd} ln det A(x): the
+ * factor (det A_oo)^2 of det(M^dag M) = (det A_oo)^2 det(Mhat^dag Mhat) that
+ * the even-site pseudofermion does not cover (two flavours).  ln det A comes
+ * from the Cholesky pivots of the last qcd_build_clover / qcd_load_clover;
+ * the derivative (G_dev, F_dev as in qcd_gauge_action_force, may be NULL)
+ * is that of the clover term built from the loaded links (zero for
+ * c_sw = 0).  Waits for its work.  QCD_ESTATE without a clover term. */
+int qcd_clover_det_action_force(qcd_ctx *ctx, double *S, void *G_dev, double *F_dev);
+
+typedef struct {
+  double dt;        /* leapfrog step                                                  */
+  double beta;      /* Wilson gauge coupling; 0 drops the gauge action                */
+  double n_f;       /* flavours (>= 0): fermion and determinant forces weigh n_f / 2  */
+  int n_steps;      /* >= 1; one noise vector per step                                */
+  int clover_det;   /* 1: include S_det = -2 sum_odd ln det A; 0: leave it out       */
+  int reunitarize;  /* 1: project the links back to SU(3) after every step            */
+} qcd_md_params;
+
+/* One trajectory of the R algorithm for n_f flavours (Gottlieb, Liu,
+ * Toussaint, Renken, Sugar, Phys. Rev. D 35 (1987) 2531; the update the
+ * paper's application runs, section 1): n_steps leapfrog steps, each
+ *   U <- exp(i (n_f/2) dt/2 P) U;     phi = Mhat^dag(U) xi_k;
+ *   U <- exp(i (1 - n_f/2) dt/2 P) U;
+ *   P <- P - dt [(n_f/2) (F_f(U, phi) + F_det(U)) + F_g(U)];
+ *   U <- exp(i dt/2 P) U                (then Gram-Schmidt back to SU(3)
+ *                                         if reunitarize: row 0 normalised,
+ *                                         row 1 orthogonalised and
+ *                                         normalised, row 2 = conj(r0 x r1)),
+ * with F_f the force of qcd_action_force, F_det that of
+ * qcd_clover_det_action_force and F_g that of qcd_gauge_action_force.  At
+ * n_f = 2 phi is refreshed at the step's midpoint; at n_f = 0 the fermion
+ * field drops out (params and xi_dev are then not read).
+ * U_dev: complex128 [V][4][3][3], in/out.  P_dev: float64 [V][4][8], in/out.
+ * xi_dev: complex128 [n_steps][Vh][4][3] on even sites.  actions (host, may
+ * be NULL): float64 [n_steps][3] receives (S_f, S_g, S_det) at each step's
+ * force evaluation, unweighted.  stats (may be NULL): the sum over the
+ * step's solves; seconds of the whole trajectory.  Waits for its work.  On
+ * return the context holds the final U (and for n_f > 0 its clover term).
+ * QCD_ENOCONV if any solve missed tol (the trajectory still completes). */
+int qcd_md_trajectory(qcd_ctx *ctx, const qcd_md_params *md, void *U_dev, double *P_dev, const void *xi_dev,
+                      const qcd_solver_params *params, double *actions, qcd_solver_stats *stats);
 
 /* Reference encoder of the mixed solver's spinor storage, for checking:
  * in_dev complex128 [n][4][3] -> codes_dev binary16 [n][24] (re, im

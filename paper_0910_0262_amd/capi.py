@@ -47,6 +47,11 @@ class SolverStats(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class MDParams(ctypes.Structure):
+    _fields_ = [("dt", ctypes.c_double), ("beta", ctypes.c_double), ("n_f", ctypes.c_double),
+                ("n_steps", ctypes.c_int), ("clover_det", ctypes.c_int), ("reunitarize", ctypes.c_int)]
+
+
 _lock = threading.Lock()
 _lib = None
 
@@ -71,6 +76,10 @@ SIGNATURES = {
                           ctypes.POINTER(SolverStats)], _I),
     "qcd_hmd_step": ([_P, _D, _P, _P, _P, ctypes.POINTER(SolverParams), ctypes.POINTER(_D),
                       ctypes.POINTER(SolverStats)], _I),
+    "qcd_gauge_action_force": ([_P, _D, ctypes.POINTER(_D), _P, _P], _I),
+    "qcd_clover_det_action_force": ([_P, ctypes.POINTER(_D), _P, _P], _I),
+    "qcd_md_trajectory": ([_P, ctypes.POINTER(MDParams), _P, _P, _P, ctypes.POINTER(SolverParams),
+                           ctypes.POINTER(_D), ctypes.POINTER(SolverStats)], _I),
     "qcd_encode_half": ([_P, _I, _P, _P, _P], _I),
     "qcd_time_stencil": ([_P, _I, _I, ctypes.POINTER(ctypes.c_double)], _I),
     "qcd_stream_copy": ([_P, _P, _P, ctypes.c_uint64], _I),
@@ -209,6 +218,42 @@ def qcd_hmd_step(ctx, dt: float, U: torch.Tensor, P: torch.Tensor, xi: torch.Ten
                              _ptr(xi, torch.complex128, volume // 2 * 12, "xi"), ctypes.byref(params),
                              ctypes.byref(s), ctypes.byref(st)))
     return s.value, st.as_dict()
+
+
+def qcd_gauge_action_force(ctx, beta: float, G: torch.Tensor | None, F: torch.Tensor | None,
+                           volume: int) -> float:
+    s = ctypes.c_double(0.0)
+    check(lib().qcd_gauge_action_force(ctx, float(beta), ctypes.byref(s),
+                                       _ptr(G, torch.complex128, volume * 36, "G"),
+                                       _ptr(F, torch.float64, volume * 32, "F")))
+    return s.value
+
+
+def qcd_clover_det_action_force(ctx, G: torch.Tensor | None, F: torch.Tensor | None, volume: int) -> float:
+    s = ctypes.c_double(0.0)
+    check(lib().qcd_clover_det_action_force(ctx, ctypes.byref(s), _ptr(G, torch.complex128, volume * 36, "G"),
+                                            _ptr(F, torch.float64, volume * 32, "F")))
+    return s.value
+
+
+def make_md_params(dt: float, n_steps: int, beta: float = 0.0, n_f: float = 2.0, clover_det: bool = True,
+                   reunitarize: bool = False) -> MDParams:
+    return MDParams(float(dt), float(beta), float(n_f), int(n_steps), int(bool(clover_det)), int(bool(reunitarize)))
+
+
+def qcd_md_trajectory(ctx, md: MDParams, U: torch.Tensor, P: torch.Tensor, xi: torch.Tensor | None,
+                      params: SolverParams | None, volume: int, raise_on_noconv: bool = True):
+    """Returns (status, actions [n_steps][3] as a list of tuples, stats dict)."""
+    st = SolverStats()
+    acts = (ctypes.c_double * (3 * md.n_steps))()
+    rc = lib().qcd_md_trajectory(ctx, ctypes.byref(md), _ptr(U, torch.complex128, volume * 36, "U"),
+                                 _ptr(P, torch.float64, volume * 32, "P"),
+                                 _ptr(xi, torch.complex128, md.n_steps * (volume // 2) * 12, "xi"),
+                                 ctypes.byref(params) if params is not None else None, acts, ctypes.byref(st))
+    if rc != QCD_OK and (raise_on_noconv or rc != QCD_ENOCONV):
+        check(rc)
+    out = [(acts[3 * k], acts[3 * k + 1], acts[3 * k + 2]) for k in range(md.n_steps)]
+    return rc, out, st.as_dict()
 
 
 def qcd_encode_half(ctx, src: torch.Tensor, codes: torch.Tensor, scale: torch.Tensor) -> None:

@@ -91,6 +91,7 @@ struct qcd_ctx {
   double2* xi = nullptr;       // clover-force Xi: [par][6][9][stride]
   double2* gint = nullptr;     // force accumulator: [mu][par][9][stride]
   double* fbuf = nullptr;      // su(3) force [V][4][8] for the HMD step
+  double* logdet = nullptr;    // ln det A(x) per odd site, from the last clover inversion
 
   // 64-thread workgroups measured fastest for the stencils at 32^3x64
   int block() const { return block_opt ? block_opt : 64; }
@@ -141,6 +142,7 @@ void free_ctx(qcd_ctx* c) {
   f(c->xi);
   f(c->gint);
   f(c->fbuf);
+  f(c->logdet);
   if (c->st_host) (void)hipHostFree(c->st_host);
   if (c->status_host) (void)hipHostFree(c->status_host);
   if (c->mbox_host) (void)hipHostFree(c->mbox_host);
@@ -645,6 +647,7 @@ int qcd_create(const int dims[4], int device, uintptr_t hip_stream, qcd_ctx** ou
     A(&c->hs[k], S * sizeof(float));
   }
   A(&c->x32, 6 * S * sizeof(float4));
+  A(&c->logdet, S * sizeof(double));
   c->n_partial = g.Vh / 64 + 64;
   A(&c->partial, (size_t)c->n_partial * sizeof(double));
 
@@ -746,7 +749,7 @@ int qcd_store_gauge(qcd_ctx* c, void* U_dev) {
 static int invert_clover(qcd_ctx* c) {
   HIPCHK(hipMemsetAsync(c->status, 0, sizeof(int), c->stream));
   HIPCHK(launch_clover_invert(c->g, c->clov, c->clov_inv, c->clov32_e, c->clovinv32_o, c->clovh_e, c->clovh_es,
-                              c->clovinvh_o, c->clovinvh_os, c->status, c->stream));
+                              c->clovinvh_o, c->clovinvh_os, c->logdet, c->status, c->stream));
   HIPCHK(hipMemcpyAsync(c->status_host, c->status, sizeof(int), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
   if (*c->status_host != 0) {
@@ -896,7 +899,10 @@ int qcd_solve(qcd_ctx* c, const qcd_solver_params* p, const void* b_dev, void* x
 }
 
 // Force pipeline on the current context state; phi in V_RHS (even sites).
-static int force_core(qcd_ctx* c, const qcd_solver_params* p, double* S, CgCounters& cnt, int* conv_rc) {
+// The fermion part of the force enters with weight wf; with det the
+// derivative of -2 sum_odd ln det A, also weighted wf, joins the clover part.
+static int force_core(qcd_ctx* c, const qcd_solver_params* p, double* S, CgCounters& cnt, int* conv_rc,
+                      double wf = 1.0, bool det = false) {
   const Geom& g = c->g;
   const int nb = nblocks(c);
   if (!c->xi) QCHK(dalloc(&c->xi, (size_t)2 * 6 * 9 * g.stride * sizeof(double2)));
@@ -926,10 +932,11 @@ static int force_core(qcd_ctx* c, const qcd_solver_params* p, double* S, CgCount
     HIPCHK(launch_dslash(g, op, c->block(), c->stream));
   }
   const double k2 = c->kappa * c->kappa;
-  HIPCHK(launch_force_hop(g, c->u18, c->f64(V_Y), c->f64(V_W), c->f64(V_X), c->f64(V_Z), 2.0 * k2, c->gint,
+  HIPCHK(launch_force_hop(g, c->u18, c->f64(V_Y), c->f64(V_W), c->f64(V_X), c->f64(V_Z), 2.0 * k2 * wf, c->gint,
                           c->stream));
   if (c->csw != 0.0) {
-    HIPCHK(launch_clover_xi(g, c->f64(V_Y), c->f64(V_W), c->f64(V_X), c->f64(V_Z), 1.0, k2, c->xi, c->stream));
+    HIPCHK(launch_clover_xi(g, c->f64(V_Y), c->f64(V_W), c->f64(V_X), c->f64(V_Z), wf, wf * k2,
+                            det ? c->clov_inv : nullptr, wf, c->xi, c->stream));
     HIPCHK(launch_force_clover(g, c->u18, c->xi, 0.5 * c->kappa * c->csw, c->gint, c->stream));
   }
   return QCD_OK;
@@ -988,6 +995,154 @@ int qcd_hmd_step(qcd_ctx* c, double dt, void* U_dev, double* P_dev, const void* 
   const double seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   fill_stats(c, cnt, p, seconds, -1.0, stats);
   if (conv != QCD_OK) return fail(QCD_ENOCONV, "force solve reached max_iter without meeting tol");
+  return QCD_OK;
+}
+
+// beta sum (1 - Re tr P / 3) (synchronises; overwrites the host state mirror)
+static int gauge_action_sync(qcd_ctx* c, double beta, double* S) {
+  HIPCHK(launch_plaquette(c->g, c->u18, c->partial, c->block(), c->stream));
+  HIPCHK(launch_fin_scalar(c->st, c->partial, nblocks(c), c->stream));
+  QCHK(sync_state(c));
+  *S = beta * c->st_host->scalar;
+  return QCD_OK;
+}
+
+// -2 sum_odd ln det A from the last inversion (synchronises)
+static int det_action_sync(qcd_ctx* c, double* S) {
+  HIPCHK(launch_sum_cb(c->g, c->logdet, c->partial, c->block(), c->stream));
+  HIPCHK(launch_fin_scalar(c->st, c->partial, nblocks(c), c->stream));
+  QCHK(sync_state(c));
+  *S = -2.0 * c->st_host->scalar;
+  return QCD_OK;
+}
+
+static int ensure_force_buffers(qcd_ctx* c) {
+  const Geom& g = c->g;
+  if (!c->xi) QCHK(dalloc(&c->xi, (size_t)2 * 6 * 9 * g.stride * sizeof(double2)));
+  if (!c->gint) QCHK(dalloc(&c->gint, (size_t)8 * 9 * g.stride * sizeof(double2)));
+  return QCD_OK;
+}
+
+int qcd_gauge_action_force(qcd_ctx* c, double beta, double* S, void* G_dev, double* F_dev) {
+  QCHK(check_ctx(c));
+  if (!std::isfinite(beta)) return fail(QCD_EINVAL, "beta must be finite");
+  QCHK(need_gauge(c));
+  QCHK(ensure_force_buffers(c));
+  if (S) QCHK(gauge_action_sync(c, beta, S));
+  if (G_dev || F_dev) {
+    HIPCHK(launch_gauge_force(c->g, c->u18, -beta / 3.0, 0, c->gint, c->stream));
+    HIPCHK(launch_force_out(c->g, c->u18, c->gint, (double2*)G_dev, F_dev, c->stream));
+  }
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return QCD_OK;
+}
+
+int qcd_clover_det_action_force(qcd_ctx* c, double* S, void* G_dev, double* F_dev) {
+  QCHK(check_ctx(c));
+  QCHK(need_clover(c));
+  QCHK(ensure_force_buffers(c));
+  if (S) QCHK(det_action_sync(c, S));
+  if (G_dev || F_dev) {
+    const Geom& g = c->g;
+    HIPCHK(launch_force_zero(g, c->gint, c->stream));
+    if (c->csw != 0.0) {
+      HIPCHK(launch_clover_xi(g, SpF64{nullptr, g.stride}, SpF64{nullptr, g.stride}, SpF64{nullptr, g.stride},
+                              SpF64{nullptr, g.stride}, 0.0, 0.0, c->clov_inv, 1.0, c->xi, c->stream));
+      HIPCHK(launch_force_clover(g, c->u18, c->xi, 0.5 * c->kappa * c->csw, c->gint, c->stream));
+    }
+    HIPCHK(launch_force_out(g, c->u18, c->gint, (double2*)G_dev, F_dev, c->stream));
+  }
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return QCD_OK;
+}
+
+// U <- exp(i h P) U on the packed links (h = 0 leaves them untouched)
+static int move_links(qcd_ctx* c, const double* P_dev, double h, bool reunit) {
+  if (h != 0.0) HIPCHK(launch_link_exp(c->g, c->u18, P_dev, h, c->stream));
+  if (reunit) HIPCHK(launch_reunitarize(c->g, c->u18, c->stream));
+  HIPCHK(launch_derive_links(c->g, c->u18, c->u12, c->uh, c->stream));
+  c->gauge_loaded = true;
+  c->clover_ready = false;
+  return QCD_OK;
+}
+
+int qcd_md_trajectory(qcd_ctx* c, const qcd_md_params* md, void* U_dev, double* P_dev, const void* xi_dev,
+                      const qcd_solver_params* p, double* actions, qcd_solver_stats* stats) {
+  QCHK(check_ctx(c));
+  if (!md) return fail(QCD_EINVAL, "null md params");
+  if (!U_dev || !P_dev) return fail(QCD_EINVAL, "null pointer");
+  if (md->n_steps < 1) return fail(QCD_EINVAL, "n_steps must be >= 1");
+  if (!std::isfinite(md->dt) || !std::isfinite(md->beta) || !std::isfinite(md->n_f) || md->n_f < 0.0)
+    return fail(QCD_EINVAL, "dt, beta must be finite and n_f finite and >= 0");
+  if ((md->clover_det != 0 && md->clover_det != 1) || (md->reunitarize != 0 && md->reunitarize != 1))
+    return fail(QCD_EINVAL, "clover_det and reunitarize must be 0 or 1");
+  const double wf = 0.5 * md->n_f;
+  const bool ferm = wf != 0.0, det = md->clover_det == 1 && wf != 0.0;
+  if (ferm) {
+    QCHK(validate_params(p));
+    if (!xi_dev) return fail(QCD_EINVAL, "null noise pointer");
+  }
+  const auto t0 = std::chrono::steady_clock::now();
+  const Geom& g = c->g;
+  const double dt = md->dt;
+  QCHK(ensure_force_buffers(c));
+  if (!c->fbuf) QCHK(dalloc(&c->fbuf, (size_t)32 * g.V * sizeof(double)));
+  HIPCHK(launch_pack_gauge(g, (const double2*)U_dev, c->u18, c->stream));
+  c->gauge_loaded = true;
+  c->clover_ready = false;
+  CgCounters cnt;
+  int conv_all = QCD_OK;
+  for (int k = 0; k < md->n_steps; ++k) {
+    double s_f = 0.0, s_g = 0.0, s_d = 0.0;
+    if (ferm) {
+      // pseudofermion refresh at U(t + (n_f/2) dt/2), then on to the midpoint
+      QCHK(move_links(c, P_dev, wf * 0.5 * dt, false));
+      QCHK(qcd_build_clover(c));
+      const double2* xi_k = (const double2*)xi_dev + (size_t)k * g.Vh * 12;
+      HIPCHK(launch_pack_spinor_cb(g, xi_k, c->f64(V_IN_E), c->stream));
+      QCHK(k1_f64(c, V_IN_E, V_T, true, nullptr));
+      QCHK(k2_f64(c, V_IN_E, V_T, V_RHS, true, 0, 0, 0.0, false, nullptr));
+      const double h2 = (1.0 - wf) * 0.5 * dt;
+      if (h2 != 0.0) {
+        QCHK(move_links(c, P_dev, h2, false));
+        QCHK(qcd_build_clover(c));
+      }
+    } else {
+      QCHK(move_links(c, P_dev, 0.5 * dt, false));
+    }
+    if (md->beta != 0.0) QCHK(gauge_action_sync(c, md->beta, &s_g));
+    if (det) QCHK(det_action_sync(c, &s_d));
+    if (ferm) {
+      int conv = QCD_OK;
+      QCHK(force_core(c, p, &s_f, cnt, &conv, wf, det));
+      if (conv != QCD_OK) conv_all = conv;
+    } else {
+      HIPCHK(launch_force_zero(g, c->gint, c->stream));
+    }
+    if (md->beta != 0.0) HIPCHK(launch_gauge_force(g, c->u18, -md->beta / 3.0, 1, c->gint, c->stream));
+    HIPCHK(launch_force_out(g, c->u18, c->gint, nullptr, c->fbuf, c->stream));
+    HIPCHK(launch_mom_update(g, P_dev, c->fbuf, dt, c->stream));
+    QCHK(move_links(c, P_dev, 0.5 * dt, md->reunitarize == 1));
+    if (actions) {
+      actions[3 * k] = s_f;
+      actions[3 * k + 1] = s_g;
+      actions[3 * k + 2] = s_d;
+    }
+  }
+  HIPCHK(launch_unpack_gauge(g, c->u18, (double2*)U_dev, c->stream));
+  if (ferm) QCHK(qcd_build_clover(c));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  const double seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (stats) {
+    if (ferm) {
+      fill_stats(c, cnt, p, seconds, -1.0, stats);
+    } else {
+      std::memset(stats, 0, sizeof(*stats));
+      stats->converged = 1;
+      stats->seconds = seconds;
+    }
+  }
+  if (conv_all != QCD_OK) return fail(QCD_ENOCONV, "a force solve reached max_iter without meeting tol");
   return QCD_OK;
 }
 

@@ -122,15 +122,18 @@ hipError_t launch_clover_build(const Geom& g, const double2* u18, double kappa, 
 
 // ------------------------------------------------------------------ inversion
 // Hermitian positive-definite 6x6 inverse by Cholesky A = L L^dag:
-// A^{-1} = L^{-dag} L^{-1}.  Returns false if a pivot is not positive.
-__device__ bool invert_block(const Block<double>& a, Block<double>& inv) {
+// A^{-1} = L^{-dag} L^{-1}, and ln det A = sum_j ln L_jj^2.  Returns false if
+// a pivot is not positive.
+__device__ bool invert_block(const Block<double>& a, Block<double>& inv, double& logdet) {
   Cx<double> L[6][6];
+  logdet = 0.0;
 #pragma unroll
   for (int j = 0; j < 6; ++j) {
     double d = a.d[j];
 #pragma unroll
     for (int k = 0; k < j; ++k) d -= norm2(L[j][k]);
     if (!(d > 0.0)) return false;
+    logdet += log(d);
     const double ljj = sqrt(d), rinv = 1.0 / ljj;
     L[j][j] = {ljj, 0.0};
 #pragma unroll
@@ -223,7 +226,8 @@ __device__ void store_site_low(const Block<double> blk[2], float4* f32, uint4* h
 __global__ void __launch_bounds__(64) clover_invert_k(Geom g, const double2* __restrict__ clov,
                                                       double2* __restrict__ clov_inv, float4* clov32_e,
                                                       float4* clovinv32_o, uint4* clovh_e, float2* clovh_es,
-                                                      uint4* clovinvh_o, float2* clovinvh_os, int* status) {
+                                                      uint4* clovinvh_o, float2* clovinvh_os,
+                                                      double* __restrict__ logdet, int* status) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= g.Vh) return;
   const CloverF64 ce{clov, g.stride}, co{clov + (size_t)36 * g.stride, g.stride};
@@ -236,9 +240,13 @@ __global__ void __launch_bounds__(64) clover_invert_k(Geom g, const double2* __r
   load_block(co, i, 0, a[0]);
   load_block(co, i, 1, a[1]);
   bool ok = true;
+  double ld_site = 0.0;
 #pragma unroll 1
   for (int b = 0; b < 2; ++b) {
-    if (!invert_block(a[b], inv[b])) {
+    double ld = 0.0;
+    if (invert_block(a[b], inv[b], ld)) {
+      ld_site += ld;
+    } else {
       ok = false;
       for (int k = 0; k < 6; ++k) inv[b].d[k] = 0.0;
       for (int k = 0; k < 15; ++k) inv[b].o[k] = {0.0, 0.0};
@@ -246,14 +254,15 @@ __global__ void __launch_bounds__(64) clover_invert_k(Geom g, const double2* __r
     store_block_f64(clov_inv + (size_t)(b * 18) * g.stride, g.stride, i, inv[b]);
   }
   store_site_low(inv, clovinv32_o, clovinvh_o, clovinvh_os, g.stride, i);
+  logdet[i] = ok ? ld_site : 0.0;
   if (!ok) *status = 1;
 }
 
 hipError_t launch_clover_invert(const Geom& g, const double2* clov, double2* clov_inv, float4* clov32_e,
                                 float4* clovinv32_o, uint4* clovh_e, float2* clovh_es, uint4* clovinvh_o,
-                                float2* clovinvh_os, int* status, hipStream_t s) {
+                                float2* clovinvh_os, double* logdet, int* status, hipStream_t s) {
   hipLaunchKernelGGL(clover_invert_k, dim3(blocks_for(g.Vh, 64)), dim3(64), 0, s, g, clov, clov_inv, clov32_e,
-                     clovinv32_o, clovh_e, clovh_es, clovinvh_o, clovinvh_os, status);
+                     clovinv32_o, clovh_e, clovh_es, clovinvh_o, clovinvh_os, logdet, status);
   return hipGetLastError();
 }
 

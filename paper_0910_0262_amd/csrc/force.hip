@@ -133,16 +133,55 @@ __device__ __forceinline__ void pauli(int k, double sgn, const Cx<double> a[3], 
   }
 }
 
+// Entry B(r, c) of one packed Hermitian 6x6 block (plain loads: each entry is
+// read by several planes).
+__device__ __forceinline__ Cx<double> blk_at(const double2* base, int stride, int i, int r, int c) {
+  if (r == c) {
+    const double2 d = base[(size_t)(r >> 1) * stride + i];
+    return {(r & 1) ? d.y : d.x, 0.0};
+  }
+  const int a = r < c ? r : c, b = r < c ? c : r;
+  const double2 o = base[(size_t)(3 + offd(a, b)) * stride + i];
+  return r < c ? Cx<double>{o.x, o.y} : Cx<double>{o.x, -o.y};
+}
+// Gamma(x)_ij += w sum_{s,s'} (sgn s_k)_{s s'} B_{(s' i),(s j)} for one chiral
+// block B (local spins 0, 1) whose sigma_mu,nu block is sgn times Pauli s_k.
+__device__ __forceinline__ void det_gamma_acc(Mat<double>& G, const double2* base, int stride, int i, int k,
+                                              double w) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      Cx<double> v;
+      if (k == 1) {
+        v = blk_at(base, stride, i, 3 + a, b) + blk_at(base, stride, i, a, 3 + b);
+      } else if (k == 2) {
+        v = tmi(blk_at(base, stride, i, 3 + a, b)) + ti(blk_at(base, stride, i, a, 3 + b));
+      } else {
+        v = blk_at(base, stride, i, a, b) - blk_at(base, stride, i, 3 + a, 3 + b);
+      }
+      G.m[a][b] = G.m[a][b] + w * v;
+    }
+}
+
+// Xi per site and plane.  FERM: Lambda = r l^dag with weight w_e (even) or w_o
+// (odd).  DET: Lambda += w_det A_oo^{-1} on odd sites (the derivative of
+// -2 sum_odd ln det A has the same form as the fermion clover term, with
+// A_oo^{-1} in place of kappa^2 Z W^dag).
+template <bool FERM, bool DET>
 __global__ void __launch_bounds__(128) clover_xi_k(Geom g, SpF64 le, SpF64 lo, SpF64 re, SpF64 ro, double w_e,
-                                                   double w_o, double2* __restrict__ xi) {
+                                                   double w_o, const double2* __restrict__ cinv, double w_det,
+                                                   double2* __restrict__ xi) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= g.V) return;
   int x[4];
   lex_coords(i, g, x);
   const int par = parity_of(x), cb = i >> 1;
   Spinor<double> l, r;
-  load(par ? lo : le, cb, l);
-  load(par ? ro : re, cb, r);
+  if constexpr (FERM) {
+    load(par ? lo : le, cb, l);
+    load(par ? ro : re, cb, r);
+  }
   const double w = par ? w_o : w_e;
   // (k_up, sign_up, k_dn, sign_dn) for each plane
   const int ku[6] = {3, 2, 1, 1, 2, 3};
@@ -151,16 +190,24 @@ __global__ void __launch_bounds__(128) clover_xi_k(Geom g, SpF64 le, SpF64 lo, S
   const double sd[6] = {-1, 1, -1, -1, -1, -1};
 #pragma unroll
   for (int p = 0; p < 6; ++p) {
-    Spinor<double> sr;
-    pauli(ku[p], su[p], r.v[0], r.v[1], sr.v[0], sr.v[1]);
-    pauli(kd[p], sd[p], r.v[2], r.v[3], sr.v[2], sr.v[3]);
     Mat<double> G = mzero<double>();
+    if constexpr (FERM) {
+      Spinor<double> sr;
+      pauli(ku[p], su[p], r.v[0], r.v[1], sr.v[0], sr.v[1]);
+      pauli(kd[p], sd[p], r.v[2], r.v[3], sr.v[2], sr.v[3]);
 #pragma unroll
-    for (int s = 0; s < 4; ++s)
+      for (int s = 0; s < 4; ++s)
 #pragma unroll
-      for (int a = 0; a < 3; ++a)
+        for (int a = 0; a < 3; ++a)
 #pragma unroll
-        for (int b = 0; b < 3; ++b) G.m[a][b] = G.m[a][b] + sr.v[s][a] * conj(l.v[s][b]);
+          for (int b = 0; b < 3; ++b) G.m[a][b] = G.m[a][b] + w * (sr.v[s][a] * conj(l.v[s][b]));
+    }
+    if constexpr (DET) {
+      if (par) {
+        det_gamma_acc(G, cinv, g.stride, cb, ku[p], w_det * su[p]);
+        det_gamma_acc(G, cinv + (size_t)18 * g.stride, g.stride, cb, kd[p], w_det * sd[p]);
+      }
+    }
     const Cx<double> tr = {(G.m[0][0].re + G.m[1][1].re + G.m[2][2].re) / 3.0,
                            (G.m[0][0].im + G.m[1][1].im + G.m[2][2].im) / 3.0};
 #pragma unroll
@@ -169,15 +216,26 @@ __global__ void __launch_bounds__(128) clover_xi_k(Geom g, SpF64 le, SpF64 lo, S
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
-      for (int b = 0; b < 3; ++b) X.m[a][b] = (0.5 * w) * (G.m[a][b] + conj(G.m[b][a]));
+      for (int b = 0; b < 3; ++b) X.m[a][b] = 0.5 * (G.m[a][b] + conj(G.m[b][a]));
     store_mat(xi + (size_t)((par * 6 + p) * 9) * g.stride, g.stride, cb, X);
   }
 }
 
 hipError_t launch_clover_xi(const Geom& g, SpF64 ell_e, SpF64 ell_o, SpF64 rho_e, SpF64 rho_o, double w_e,
-                            double w_o, double2* xi, hipStream_t s) {
-  hipLaunchKernelGGL(clover_xi_k, dim3(blocks_for(g.V, 128)), dim3(128), 0, s, g, ell_e, ell_o, rho_e, rho_o, w_e,
-                     w_o, xi);
+                            double w_o, const double2* cinv, double w_det, double2* xi, hipStream_t s) {
+  const dim3 grid(blocks_for(g.V, 128)), block(128);
+  const bool ferm = ell_e.p != nullptr, det = cinv != nullptr;
+  if (ferm && det)
+    hipLaunchKernelGGL((clover_xi_k<true, true>), grid, block, 0, s, g, ell_e, ell_o, rho_e, rho_o, w_e, w_o, cinv,
+                       w_det, xi);
+  else if (ferm)
+    hipLaunchKernelGGL((clover_xi_k<true, false>), grid, block, 0, s, g, ell_e, ell_o, rho_e, rho_o, w_e, w_o, cinv,
+                       w_det, xi);
+  else if (det)
+    hipLaunchKernelGGL((clover_xi_k<false, true>), grid, block, 0, s, g, ell_e, ell_o, rho_e, rho_o, w_e, w_o, cinv,
+                       w_det, xi);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
@@ -255,6 +313,154 @@ __global__ void __launch_bounds__(64) force_clover_k(Geom g, const double2* __re
 hipError_t launch_force_clover(const Geom& g, const double2* u18, const double2* xi, double coef, double2* gint,
                                hipStream_t s) {
   hipLaunchKernelGGL(force_clover_k, dim3(blocks_for(4 * g.V, 64)), dim3(64), 0, s, g, u18, xi, coef, gint);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ Wilson gauge action and force
+// S_g = beta sum_{x, mu<nu} (1 - Re tr U_mu,nu(x) / 3).  For one link the
+// plaquettes through it sum to Re tr(U_mu(x) A_mu(x)) with the staple sum
+//   A_mu(x) = sum_{nu != mu} U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag
+//                          + U_nu(x+mu-nu)^dag U_mu(x-nu)^dag U_nu(x-nu),
+// so dS_g = -(beta/3) Re tr(dU A) and G = -(beta/3) A^dag.
+__device__ __forceinline__ Mat<double> staple_sum(const double2* u18, const Geom& g, int mu, const int y[4]) {
+  Mat<double> a = mzero<double>();
+#pragma unroll 1
+  for (int nu = 0; nu < 4; ++nu) {
+    if (nu == mu) continue;
+    int ypm[4], ypn[4], ymn[4], ypmmn[4];
+    shift4(g, y, mu, 1, ypm);
+    shift4(g, y, nu, 1, ypn);
+    shift4(g, y, nu, -1, ymn);
+    shift4(g, ypm, nu, -1, ypmmn);
+    const Mat<double> up = mm(mm(u_at(u18, g, nu, ypm), adj(u_at(u18, g, mu, ypn))), adj(u_at(u18, g, nu, y)));
+    const Mat<double> dn = mm(adj(mm(u_at(u18, g, mu, ymn), u_at(u18, g, nu, ypmmn))), u_at(u18, g, nu, ymn));
+    a = madd(a, madd(up, dn));
+  }
+  return a;
+}
+
+// gint(mu, x) (+)= coef A_mu(x)^dag; one thread per link.
+__global__ void __launch_bounds__(64) gauge_force_k(Geom g, const double2* __restrict__ u18, double coef,
+                                                    int accumulate, double2* __restrict__ gint) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 4 * g.V) return;
+  const int mu = t / g.V, i = t - mu * g.V;
+  int y[4];
+  lex_coords(i, g, y);
+  const int par = parity_of(y), cb = i >> 1;
+  const Mat<double> a = staple_sum(u18, g, mu, y);
+  double2* base = gint + (size_t)((mu * 2 + par) * 9) * g.stride;
+  Mat<double> gm = accumulate ? load_mat(base, g.stride, cb) : mzero<double>();
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) gm.m[r][c] = gm.m[r][c] + coef * conj(a.m[c][r]);
+  store_mat(base, g.stride, cb, gm);
+}
+
+hipError_t launch_gauge_force(const Geom& g, const double2* u18, double coef, int accumulate, double2* gint,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(gauge_force_k, dim3(blocks_for(4 * g.V, 64)), dim3(64), 0, s, g, u18, coef, accumulate, gint);
+  return hipGetLastError();
+}
+
+// Per-block partial sums of sum_{mu<nu} (1 - Re tr U_mu,nu(x) / 3); thread t
+// covers the two sites 2t and 2t + 1 (one of each parity).
+__global__ void __launch_bounds__(256) plaquette_k(Geom g, const double2* __restrict__ u18, double* partial) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  double acc = 0.0;
+  if (t < g.Vh) {
+#pragma unroll 1
+    for (int k = 0; k < 2; ++k) {
+      int x[4];
+      lex_coords(2 * t + k, g, x);
+#pragma unroll 1
+      for (int mu = 0; mu < 3; ++mu)
+#pragma unroll 1
+        for (int nu = mu + 1; nu < 4; ++nu) {
+          int xpm[4], xpn[4];
+          shift4(g, x, mu, 1, xpm);
+          shift4(g, x, nu, 1, xpn);
+          const Mat<double> a = mm(u_at(u18, g, mu, x), u_at(u18, g, nu, xpm));
+          const Mat<double> b = mm(u_at(u18, g, nu, x), u_at(u18, g, mu, xpn));
+          // Re tr(a b^dag) = sum_rc Re(a_rc conj(b_rc))
+          double re = 0.0;
+#pragma unroll
+          for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) re += a.m[r][c].re * b.m[r][c].re + a.m[r][c].im * b.m[r][c].im;
+          acc += 1.0 - re / 3.0;
+        }
+    }
+  }
+  block_sum_store(acc, partial, blockIdx.x);
+}
+
+hipError_t launch_plaquette(const Geom& g, const double2* u18, double* partial, int block, hipStream_t s) {
+  hipLaunchKernelGGL(plaquette_k, dim3(blocks_for(g.Vh, block)), dim3(block), 0, s, g, u18, partial);
+  return hipGetLastError();
+}
+
+// Per-block partial sums of a checkerboard array of doubles.
+__global__ void __launch_bounds__(256) sum_cb_k(int n, const double* __restrict__ v, double* partial) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  block_sum_store(t < n ? v[t] : 0.0, partial, blockIdx.x);
+}
+
+hipError_t launch_sum_cb(const Geom& g, const double* v, double* partial, int block, hipStream_t s) {
+  hipLaunchKernelGGL(sum_cb_k, dim3(blocks_for(g.Vh, block)), dim3(block), 0, s, g.Vh, v, partial);
+  return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(256) fill_zero_k(size_t n, double2* __restrict__ p) {
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) p[t] = make_double2(0.0, 0.0);
+}
+
+hipError_t launch_force_zero(const Geom& g, double2* gint, hipStream_t s) {
+  const size_t n = (size_t)8 * 9 * g.stride;
+  hipLaunchKernelGGL(fill_zero_k, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, gint);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ reunitarisation
+// Row 0 normalised, row 1 orthogonalised against it and normalised, row 2 =
+// conj(row 0 x row 1): the nearest SU(3) matrix in the Gram-Schmidt sense.
+__global__ void __launch_bounds__(128) reunitarize_k(Geom g, double2* __restrict__ u18) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 4 * g.V) return;
+  const int mu = t / g.V, i = t - mu * g.V;
+  int x[4];
+  lex_coords(i, g, x);
+  const int par = parity_of(x), cb = i >> 1;
+  double2* base = u18 + (size_t)((mu * 2 + par) * 9) * g.stride;
+  Mat<double> u = load_mat(base, g.stride, cb);
+  double n0 = 0.0;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) n0 += norm2(u.m[0][c]);
+  n0 = 1.0 / sqrt(n0);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) u.m[0][c] = n0 * u.m[0][c];
+  Cx<double> d = {0.0, 0.0};
+#pragma unroll
+  for (int c = 0; c < 3; ++c) d = d + cmulc(u.m[0][c], u.m[1][c]);  // conj(a) b
+  double n1 = 0.0;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    u.m[1][c] = u.m[1][c] - d * u.m[0][c];
+    n1 += norm2(u.m[1][c]);
+  }
+  n1 = 1.0 / sqrt(n1);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) u.m[1][c] = n1 * u.m[1][c];
+  u.m[2][0] = conj(u.m[0][1] * u.m[1][2] - u.m[0][2] * u.m[1][1]);
+  u.m[2][1] = conj(u.m[0][2] * u.m[1][0] - u.m[0][0] * u.m[1][2]);
+  u.m[2][2] = conj(u.m[0][0] * u.m[1][1] - u.m[0][1] * u.m[1][0]);
+  store_mat(base, g.stride, cb, u);
+}
+
+hipError_t launch_reunitarize(const Geom& g, double2* u18, hipStream_t s) {
+  hipLaunchKernelGGL(reunitarize_k, dim3(blocks_for(4 * g.V, 128)), dim3(128), 0, s, g, u18);
   return hipGetLastError();
 }
 

@@ -168,17 +168,24 @@ hipError_t launch_clover_build(const Geom& g, const double2* u18, double kappa, 
                                hipStream_t s);
 hipError_t launch_clover_invert(const Geom& g, const double2* clov, double2* clov_inv, float4* clov32_e,
                                 float4* clovinv32_o, uint4* clovh_e, float2* clovh_es, uint4* clovinvh_o,
-                                float2* clovinvh_os, int* status, hipStream_t s);
+                                float2* clovinvh_os, double* logdet, int* status, hipStream_t s);
 
 // ---- force.hip
 hipError_t launch_force_hop(const Geom& g, const double2* u18, SpF64 ell_e, SpF64 ell_o, SpF64 rho_e,
                             SpF64 rho_o, double coef, double2* gint, hipStream_t s);
+// ell_e.p == nullptr drops the fermion term; cinv == nullptr the determinant term
 hipError_t launch_clover_xi(const Geom& g, SpF64 ell_e, SpF64 ell_o, SpF64 rho_e, SpF64 rho_o, double w_e,
-                            double w_o, double2* xi, hipStream_t s);
+                            double w_o, const double2* cinv, double w_det, double2* xi, hipStream_t s);
 hipError_t launch_force_clover(const Geom& g, const double2* u18, const double2* xi, double coef, double2* gint,
                                hipStream_t s);
 hipError_t launch_force_out(const Geom& g, const double2* u18, const double2* gint, double2* g_user,
                             double* f_user, hipStream_t s);
+hipError_t launch_gauge_force(const Geom& g, const double2* u18, double coef, int accumulate, double2* gint,
+                              hipStream_t s);
+hipError_t launch_plaquette(const Geom& g, const double2* u18, double* partial, int block, hipStream_t s);
+hipError_t launch_sum_cb(const Geom& g, const double* v, double* partial, int block, hipStream_t s);
+hipError_t launch_force_zero(const Geom& g, double2* gint, hipStream_t s);
+hipError_t launch_reunitarize(const Geom& g, double2* u18, hipStream_t s);
 hipError_t launch_link_exp(const Geom& g, double2* u18, const double* p_user, double c, hipStream_t s);
 hipError_t launch_mom_update(const Geom& g, double* p_user, const double* f_user, double dt, hipStream_t s);
 

@@ -121,6 +121,37 @@ class Lattice:
         p = capi.make_params(_PREC[prec], tol, max_iter, pipeline_depth, delta_reliable)
         return capi.qcd_hmd_step(self._ctx, dt, U, P, xi, p, self.V)
 
+    def gauge_action_force(self, beta: float, want_G=True, want_F=True):
+        """Wilson plaquette action S_g and its derivative (G, F) on the loaded gauge field."""
+        G, F = self._force_buffers(want_G, want_F)
+        S = capi.qcd_gauge_action_force(self._ctx, beta, G, F, self.V)
+        return S, G, F
+
+    def clover_det_action_force(self, want_G=True, want_F=True):
+        """S_det = -2 sum_odd ln det A and its derivative (G, F)."""
+        G, F = self._force_buffers(want_G, want_F)
+        S = capi.qcd_clover_det_action_force(self._ctx, G, F, self.V)
+        return S, G, F
+
+    def md_trajectory(self, U: torch.Tensor, P: torch.Tensor, xi: torch.Tensor | None, dt: float, n_steps: int,
+                      beta: float = 0.0, n_f: float = 2.0, clover_det: bool = True, reunitarize: bool = False,
+                      prec="fp64", tol=1e-12, max_iter=20000, pipeline_depth=2, delta_reliable=0.1,
+                      raise_on_noconv=True):
+        """One R-algorithm trajectory in place on U and P; xi is (n_steps, V/2, 4, 3).
+
+        Returns (actions, stats): actions[k] = (S_f, S_g, S_det) at step k's force evaluation."""
+        md = capi.make_md_params(dt, n_steps, beta, n_f, clover_det, reunitarize)
+        p = capi.make_params(_PREC[prec], tol, max_iter, pipeline_depth, delta_reliable) if n_f != 0 else None
+        rc, acts, st = capi.qcd_md_trajectory(self._ctx, md, U, P, xi, p, self.V, raise_on_noconv)
+        st["status"] = capi.STATUS_NAMES[rc]
+        return acts, st
+
+    def _force_buffers(self, want_G, want_F):
+        lx, ly, lz, lt = self.dims
+        G = torch.empty((lt, lz, ly, lx, 4, 3, 3), dtype=torch.complex128, device=self.device) if want_G else None
+        F = torch.empty((lt, lz, ly, lx, 4, 8), dtype=torch.float64, device=self.device) if want_F else None
+        return G, F
+
     def encode_half(self, psi: torch.Tensor):
         n = psi.numel() // 12
         codes = torch.empty((n, 24), dtype=torch.float16, device=self.device)

@@ -1,0 +1,184 @@
+"""GPU parity of the Wilson gauge action and force, the odd-site clover
+determinant and its force, reunitarisation and the R-algorithm trajectory
+against the oracle.
+
+Bars: the gauge and determinant parts involve no solve, so their actions and
+forces agree with the FP64 oracle to rounding (1e-12 relative to the largest
+component; 1e-11 for the determinant force, which goes through a 6x6
+Cholesky inverse).  A trajectory contains solves at tol 1e-12 and inherits
+the force bar of 1e-9."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from oracle import md
+from paper_0910_0262_amd import Lattice, QCDError, capi, synth
+
+from ._gpu_helpers import max_rel, to_dev
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    ((4, 4, 4, 8), 0.3, 0.125, 1.0, 0),
+    ((6, 2, 2, 6), 0.5, 0.124, 1.3, 1),
+    ((16, 16, 16, 16), 0.3, 0.125, 1.0, 2),
+]
+IDS = ["4x4x4x8", "6x2x2x6", "16^4"]
+BETA = 5.6
+
+
+@pytest.fixture(scope="module", params=CASES, ids=IDS)
+def case(request):
+    dims, w, k, c, seed = request.param
+    print(f"[md case dims={dims} width={w} kappa={k} csw={c} seed={seed}]", flush=True)
+    u = synth.random_su3_field(dims, w, seed)
+    lat = Lattice(dims, k, c)
+    lat.load_gauge(to_dev(u))
+    yield dims, lat, torch.as_tensor(u), (k, c)
+    lat.close()
+
+
+def test_gauge_action_force_parity(case):
+    dims, lat, u, _ = case
+    S_ref = float(md.gauge_action(u, BETA))
+    G_ref = md.gradient(lambda v: md.gauge_action(v, BETA), u)
+    F_ref = O.project_force(u, G_ref)
+    S, G, F = lat.gauge_action_force(BETA)
+    print(f"  S_g={S:.12e} oracle {S_ref:.12e}", flush=True)
+    assert abs(S - S_ref) < 1e-12 * abs(S_ref)
+    assert max_rel(G, G_ref) < 1e-12
+    assert max_rel(F, F_ref) < 1e-12
+    # action only / force only
+    S2, G2, F2 = lat.gauge_action_force(BETA, want_G=False, want_F=False)
+    assert S2 == S and G2 is None and F2 is None
+
+
+def test_clover_det_action_force_parity(case):
+    dims, lat, u, (k, c) = case
+    S_ref = float(md.clover_det_action(u, k, c))
+    G_ref = md.gradient(lambda v: md.clover_det_action(v, k, c), u)
+    F_ref = O.project_force(u, G_ref)
+    S, G, F = lat.clover_det_action_force()
+    print(f"  S_det={S:.12e} oracle {S_ref:.12e}", flush=True)
+    assert abs(S - S_ref) < 1e-12 * abs(S_ref)
+    assert max_rel(G, G_ref) < 1e-11
+    assert max_rel(F, F_ref) < 1e-11
+
+
+def test_clover_det_closed_form_and_csw0():
+    dims, kappa, csw, n = (4, 4, 2, 2), 0.13, 1.3, 1
+    lx, ly, lz, lt = dims
+    b = 2 * np.pi * n / (lx * ly)
+    lat = Lattice(dims, kappa, csw)
+    lat.load_gauge(to_dev(synth.abelian_flux_field(dims, n)))
+    S, _, _ = lat.clover_det_action_force(want_G=False, want_F=False)
+    a = kappa * csw * np.sin(b)
+    expect = -2.0 * (lx * ly * lz * lt // 2) * 4.0 * np.log(1.0 - a * a)
+    assert abs(S - expect) < 1e-12 * abs(expect)
+    # c_sw = 0: A = 1, no action, no force
+    lat.set_params(kappa, 0.0)
+    lat.load_gauge(to_dev(synth.random_su3_field(dims, 0.3, 0)))
+    S, G, F = lat.clover_det_action_force()
+    assert S == 0.0
+    assert float(torch.abs(G).max()) == 0.0 and float(torch.abs(F).max()) == 0.0
+    lat.close()
+
+
+def test_missing_state_and_bad_arguments():
+    dims = (4, 4, 4, 4)
+    lat = Lattice(dims, 0.125, 1.0)
+    with pytest.raises(QCDError, match="ESTATE"):
+        lat.gauge_action_force(BETA)
+    with pytest.raises(QCDError, match="ESTATE"):
+        lat.clover_det_action_force()
+    lat.load_gauge(to_dev(synth.random_su3_field(dims, 0.3, 0)))
+    with pytest.raises(QCDError, match="EINVAL"):
+        lat.gauge_action_force(float("nan"))
+    U = to_dev(synth.random_su3_field(dims, 0.3, 0))
+    P = to_dev(synth.momenta(dims, 0))
+    xi = to_dev(np.stack([synth.heatbath_xi(dims, 0)]))
+    with pytest.raises(QCDError, match="EINVAL"):
+        lat.md_trajectory(U, P, xi, 0.02, 1, n_f=-1.0)
+    with pytest.raises(QCDError, match="EINVAL"):
+        lat.md_trajectory(U, P, xi, float("inf"), 1)
+    with pytest.raises((QCDError, ValueError)):
+        lat.md_trajectory(U, P, None, 0.02, 1, n_f=2.0)
+    lat.close()
+
+
+TRAJ = [
+    # (n_f, clover_det, reunitarize, prec)
+    (2.0, True, False, "fp64"),
+    (1.0, True, True, "fp64"),
+    (3.0, False, False, "fp64"),
+    (2.0, True, False, "mixed"),
+    (0.0, False, True, "fp64"),
+]
+TRAJ_IDS = ["nf2-det", "nf1-det-reunit", "nf3-nodet", "nf2-det-mixed", "pure-gauge"]
+
+
+@pytest.mark.parametrize("nf,det,reunit,prec", TRAJ, ids=TRAJ_IDS)
+def test_trajectory_parity(nf, det, reunit, prec):
+    dims, w, kappa, csw, seed = (4, 4, 2, 4), 0.3, 0.125, 1.0, 7
+    n, dt = 3, 0.02
+    print(f"[trajectory n_f={nf} det={det} reunit={reunit} prec={prec}]", flush=True)
+    u0 = synth.random_su3_field(dims, w, seed)
+    p0 = synth.momenta(dims, seed)
+    xis = np.stack([synth.heatbath_xi(dims, seed + k) for k in range(n)])
+    u_ref, p_ref, acts_ref = md.trajectory(torch.as_tensor(u0), torch.as_tensor(p0),
+                                           [torch.as_tensor(x) for x in xis], dt, kappa, csw, BETA,
+                                           with_det=det, n_f=nf, reunit=reunit, tol=1e-14)
+    lat = Lattice(dims, kappa, csw)
+    U, P = to_dev(u0), to_dev(p0)
+    acts, st = lat.md_trajectory(U, P, to_dev(xis) if nf != 0 else None, dt, n, beta=BETA, n_f=nf,
+                                 clover_det=det, reunitarize=reunit, prec=prec, tol=1e-12)
+    print(f"  iters={st['iters']} seconds={st['seconds']:.3f}", flush=True)
+    assert max_rel(U, u_ref) < 1e-9
+    assert max_rel(P, p_ref) < 1e-9
+    for k in range(n):
+        if nf != 0:
+            assert abs(acts[k][0] - acts_ref[k]["fermion"]) < 1e-10 * abs(acts_ref[k]["fermion"])
+        assert abs(acts[k][1] - acts_ref[k]["gauge"]) < 1e-10 * abs(acts_ref[k]["gauge"])
+        if det:
+            assert abs(acts[k][2] - acts_ref[k]["det"]) < 1e-10 * abs(acts_ref[k]["det"])
+    eye = torch.eye(3, dtype=torch.complex128, device="cuda")
+    assert float(torch.abs(U.conj().transpose(-1, -2) @ U - eye).max()) < 1e-13
+    # the context holds the final field: the gauge action there matches the oracle's
+    S_end, _, _ = lat.gauge_action_force(BETA, want_G=False, want_F=False)
+    assert abs(S_end - float(md.gauge_action(u_ref, BETA))) < 1e-10 * S_end
+    lat.close()
+
+
+def test_reunitarize_kernel_parity():
+    """dt = 0 pure-gauge trajectory: the links only pass through the reunitarisation."""
+    dims = (4, 2, 2, 6)
+    u = synth.random_su3_field(dims, 0.5, 3)
+    rng = np.random.default_rng(4)
+    noisy = u + 1e-4 * (rng.standard_normal(u.shape) + 1j * rng.standard_normal(u.shape))
+    ref = md.reunitarize(torch.as_tensor(noisy))
+    lat = Lattice(dims, 0.125, 1.0)
+    U = to_dev(noisy)
+    P = to_dev(synth.momenta(dims, 0))
+    P0 = P.clone()
+    lat.md_trajectory(U, P, None, 0.0, 1, beta=0.0, n_f=0.0, reunitarize=True)
+    assert float(torch.abs(U.cpu() - ref).max()) < 1e-14
+    assert torch.equal(P, P0)
+    lat.close()
+
+
+def test_trajectory_matches_hmd_steps():
+    """n_f = 2, no gauge action, no determinant: the trajectory is a chain of qcd_hmd_step calls."""
+    dims, kappa, csw, dt, n = (4, 4, 4, 4), 0.125, 1.0, 0.02, 2
+    u0 = synth.random_su3_field(dims, 0.3, 5)
+    p0 = synth.momenta(dims, 5)
+    xis = np.stack([synth.heatbath_xi(dims, 5 + k) for k in range(n)])
+    lat = Lattice(dims, kappa, csw)
+    U1, P1 = to_dev(u0), to_dev(p0)
+    lat.md_trajectory(U1, P1, to_dev(xis), dt, n, beta=0.0, n_f=2.0, clover_det=False, tol=1e-12)
+    U2, P2 = to_dev(u0), to_dev(p0)
+    for k in range(n):
+        lat.hmd_step(U2, P2, to_dev(xis[k]), dt, tol=1e-12)
+    assert float(torch.abs(U1 - U2).max()) < 1e-13
+    assert float(torch.abs(P1 - P2).max()) < 1e-10
+    lat.close()
