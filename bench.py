@@ -175,6 +175,42 @@ def secondary(name, dims, width, kappa, csw, tol, reps, n_apps):
     return out
 
 
+def trajectory_run(lat, dims, u_dev, n_steps, dt, beta, prec, tol, seed=0):
+    """One R-algorithm trajectory (n_f = 2, clover determinant, gauge action,
+    reunitarisation) from u_dev with fresh momenta; not part of `value`."""
+    from paper_0910_0262_amd import synth
+
+    lx, ly, lz, lt = dims
+    U = u_dev.clone()
+    P = torch.as_tensor(synth.momenta(dims, seed)).cuda()
+    xi = torch.as_tensor(np.stack([synth.heatbath_xi(dims, seed + k) for k in range(n_steps)])).cuda()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    acts, st = lat.md_trajectory(U, P, xi, dt, n_steps, beta=beta, n_f=2.0, clover_det=True, reunitarize=True,
+                                 prec=prec, tol=tol)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    out = {"dims": list(dims), "n_steps": n_steps, "dt": dt, "beta": beta, "n_f": 2.0, "prec": prec, "tol": tol,
+           "s": t, "ms_per_md_step": 1e3 * t / n_steps, "solver_iters_per_step": st["iters"] / n_steps,
+           "actions_first": acts[0], "actions_last": acts[-1]}
+    log(f"trajectory {lx}x{ly}x{lz}x{lt}: {n_steps} steps in {t:.3f} s ({out['ms_per_md_step']:.1f} ms/step, "
+        f"{out['solver_iters_per_step']:.0f} CG iterations/step)")
+    del U, P, xi
+    return out
+
+
+def trajectory_secondary(dims, width, kappa, csw, n_steps, dt, beta, prec, tol):
+    from paper_0910_0262_amd import Lattice, synth
+
+    lat = Lattice(dims, kappa, csw)
+    u = torch.as_tensor(synth.random_su3_field(dims, width, 0)).cuda()
+    lat.load_gauge(u)
+    trajectory_run(lat, dims, u, 1, dt, beta, prec, tol)  # warm-up
+    out = trajectory_run(lat, dims, u, n_steps, dt, beta, prec, tol)
+    lat.close()
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -187,6 +223,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-force", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
+    ap.add_argument("--no-trajectory", action="store_true")
+    ap.add_argument("--beta", type=float, default=5.6, help="gauge coupling of the MD trajectories")
     ap.add_argument("--mixed-clover", type=int, default=16, choices=(16, 32))
     ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the committed traffic summary from two rocprofv3 --pmc counter CSVs and exit")
@@ -353,6 +391,9 @@ def main() -> int:
                    "8.7x / 9.6x over one 2.33 GHz Xeon core (whole application)",
     }
     out["mixed_clover_bits"] = args.mixed_clover
+    if not args.no_trajectory:
+        out["trajectory"] = {f"{lx}x{ly}x{lz}x{lt}": trajectory_run(lat, dims, U, 2, 0.02, args.beta, "mixed",
+                                                                     args.tol)}
     lat.close()
     del B, U, XI, phi
     torch.cuda.empty_cache()
@@ -361,6 +402,10 @@ def main() -> int:
             "16^4": secondary("16^4", (16, 16, 16, 16), 0.3, 0.125, csw, args.tol, 5, 100),
             "8x8x16x16": secondary("8x8x16x16", (8, 8, 16, 16), 0.5, 0.124, csw, args.tol, 5, 100),
         }
+        if not args.no_trajectory:
+            for prec in ("mixed", "fp64"):
+                out["trajectory"][f"16^4-{prec}"] = trajectory_secondary((16, 16, 16, 16), 0.3, 0.125, csw, 10,
+                                                                         0.02, args.beta, prec, args.tol)
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle Mhat^dag Mhat at the full workload")
         fp64_iters = int(round(np.mean([r["iters"] for r in rec["solves"]

@@ -13,9 +13,15 @@
 
 namespace qcd {
 
+// Each link enters the leaves of many sites: ordinary (cached) loads.
 __device__ __forceinline__ Mat<double> link_at(const double2* u18, const Geom& g, int mu, const int x[4]) {
+  const double2* base = u18 + (size_t)((mu * 2 + parity_of(x)) * 9) * g.stride + (lex(x, g) >> 1);
   Mat<double> u;
-  load_link(LinkF64<9>{u18, g.stride}, mu, parity_of(x), lex(x, g) >> 1, u);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    const double2 d = base[(size_t)k * g.stride];
+    u.m[k / 3][k % 3] = {d.x, d.y};
+  }
   return u;
 }
 __device__ __forceinline__ void shift(const Geom& g, const int x[4], int mu, int n, int y[4]) {

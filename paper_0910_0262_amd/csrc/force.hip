@@ -31,9 +31,16 @@ __device__ __forceinline__ void shift4(const Geom& g, const int x[4], int mu, in
   y[3] = x[3];
   y[mu] = (x[mu] + n + 2 * g.X[mu]) % g.X[mu];
 }
+// Links are gathered by many neighbouring threads here, so they are read
+// with ordinary (cached) loads, unlike the stencil's streaming loads.
 __device__ __forceinline__ Mat<double> u_at(const double2* u18, const Geom& g, int mu, const int x[4]) {
+  const double2* base = u18 + (size_t)((mu * 2 + parity_of(x)) * 9) * g.stride + (lex(x, g) >> 1);
   Mat<double> u;
-  load_link(LinkF64<9>{u18, g.stride}, mu, parity_of(x), lex(x, g) >> 1, u);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    const double2 d = base[(size_t)k * g.stride];
+    u.m[k / 3][k % 3] = {d.x, d.y};
+  }
   return u;
 }
 __device__ __forceinline__ void spinor_at(SpF64 e, SpF64 o, const Geom& g, const int x[4], Spinor<double>& v) {
@@ -188,7 +195,7 @@ __global__ void __launch_bounds__(128) clover_xi_k(Geom g, SpF64 le, SpF64 lo, S
   const double su[6] = {-1, 1, 1, -1, 1, 1};
   const int kd[6] = {3, 2, 1, 1, 2, 3};
   const double sd[6] = {-1, 1, -1, -1, -1, -1};
-#pragma unroll
+#pragma unroll 1
   for (int p = 0; p < 6; ++p) {
     Mat<double> G = mzero<double>();
     if constexpr (FERM) {
@@ -249,16 +256,24 @@ __device__ __forceinline__ Mat<double> xi_at(const double2* xi, const Geom& g, i
 // Derivative matrix of the four leaves of one plaquette with respect to its
 // first link: the loop continues with L1 L2 L3, and C0..C3 are Xi at the
 // start points of (link, L1, L2, L3).  tr(dQ Xi) summed over the 4 leaves
-// equals tr(dU M) with this M.
-__device__ __forceinline__ Mat<double> insertion(const Mat<double>& L1, const Mat<double>& L2, const Mat<double>& L3,
-                                                 const Mat<double>& C0, const Mat<double>& C1, const Mat<double>& C2,
-                                                 const Mat<double>& C3) {
-  const Mat<double> L12 = mm(L1, L2), L23 = mm(L2, L3), L123 = mm(L12, L3);
-  Mat<double> m = mm(L123, C0);
-  m = madd(m, mm(C1, L123));
-  m = madd(m, mm(mm(L1, C2), L23));
-  m = madd(m, mm(mm(L12, C3), L3));
-  return m;
+// equals tr(dU M) with
+//   M = L1 L2 L3 C0 + C1 L1 L2 L3 + L1 C2 L2 L3 + L1 L2 C3 L3
+//     = L1 T + C1 (L1 A),  A = L2 L3,  T = A C0 + C2 A + L2 (C3 L3).
+// The factors are fetched by the callables in the order they are needed,
+// which keeps at most four 3x3 matrices live.
+template <class F1, class F2, class F3, class G0, class G1, class G2, class G3>
+__device__ __forceinline__ Mat<double> insertion(F1 l1, F2 l2, F3 l3, G0 c0, G1 c1, G2 c2, G3 c3) {
+  Mat<double> A, T;
+  {
+    const Mat<double> L2 = l2(), L3 = l3();
+    A = mm(L2, L3);
+    T = mm(L2, mm(c3(), L3));
+  }
+  T = madd(T, mm(A, c0()));
+  T = madd(T, mm(c2(), A));
+  const Mat<double> L1 = l1();
+  Mat<double> m = mm(L1, T);
+  return madd(m, mm(c1(), mm(L1, A)));
 }
 
 __global__ void __launch_bounds__(64) force_clover_k(Geom g, const double2* __restrict__ u18,
@@ -281,21 +296,28 @@ __global__ void __launch_bounds__(64) force_clover_k(Geom g, const double2* __re
     shift4(g, y, nu, -1, ymn);
     shift4(g, ypm, nu, 1, ypmpn);
     shift4(g, ypm, nu, -1, ypmmn);
+    auto U = [&](int d, const int* c) { return u_at(u18, g, d, c); };
+    auto Ud = [&](int d, const int* c) { return adj(u_at(u18, g, d, c)); };
+    auto X = [&](const int* c) { return xi_at(xi, g, p, c); };
     Mat<double> mu_, md;
     if (mu < nu) {
       // link first in the plaquette at y (mu then nu)
-      mu_ = insertion(u_at(u18, g, nu, ypm), adj(u_at(u18, g, mu, ypn)), adj(u_at(u18, g, nu, y)), xi_at(xi, g, p, y),
-                      xi_at(xi, g, p, ypm), xi_at(xi, g, p, ypmpn), xi_at(xi, g, p, ypn));
+      mu_ = insertion([&] { return U(nu, ypm); }, [&] { return Ud(mu, ypn); }, [&] { return Ud(nu, y); },
+                      [&] { return X(y); }, [&] { return X(ypm); }, [&] { return X(ypmpn); },
+                      [&] { return X(ypn); });
       // link reversed (third) in the plaquette at y - nu
-      md = insertion(adj(u_at(u18, g, nu, ymn)), u_at(u18, g, mu, ymn), u_at(u18, g, nu, ypmmn), xi_at(xi, g, p, ypm),
-                     xi_at(xi, g, p, y), xi_at(xi, g, p, ymn), xi_at(xi, g, p, ypmmn));
+      md = insertion([&] { return Ud(nu, ymn); }, [&] { return U(mu, ymn); }, [&] { return U(nu, ypmmn); },
+                     [&] { return X(ypm); }, [&] { return X(y); }, [&] { return X(ymn); },
+                     [&] { return X(ypmmn); });
     } else {
       // plane (nu, mu): link second in the plaquette at y - nu
-      mu_ = insertion(adj(u_at(u18, g, nu, ypmmn)), adj(u_at(u18, g, mu, ymn)), u_at(u18, g, nu, ymn),
-                      xi_at(xi, g, p, y), xi_at(xi, g, p, ypm), xi_at(xi, g, p, ypmmn), xi_at(xi, g, p, ymn));
+      mu_ = insertion([&] { return Ud(nu, ypmmn); }, [&] { return Ud(mu, ymn); }, [&] { return U(nu, ymn); },
+                      [&] { return X(y); }, [&] { return X(ypm); }, [&] { return X(ypmmn); },
+                      [&] { return X(ymn); });
       // link reversed (fourth) in the plaquette at y
-      md = insertion(u_at(u18, g, nu, y), u_at(u18, g, mu, ypn), adj(u_at(u18, g, nu, ypm)), xi_at(xi, g, p, ypm),
-                     xi_at(xi, g, p, y), xi_at(xi, g, p, ypn), xi_at(xi, g, p, ypmpn));
+      md = insertion([&] { return U(nu, y); }, [&] { return U(mu, ypn); }, [&] { return Ud(nu, ypm); },
+                     [&] { return X(ypm); }, [&] { return X(y); }, [&] { return X(ypn); },
+                     [&] { return X(ypmpn); });
     }
     // reversed occurrences: Im tr(dU^dag M) = -Im tr(dU M^dag)
     mt = madd(mt, msub(mu_, adj(md)));
