@@ -172,6 +172,28 @@ typedef struct {
 int qcd_solve(qcd_ctx *ctx, const qcd_solver_params *params, const void *b_dev, void *x_dev,
               qcd_solver_stats *stats);
 
+/* Largest number of right-hand sides of one qcd_solve_multi call. */
+#define QCD_MAX_RHS 16
+
+/* n_rhs independent solves M x_k = b_k (k < n_rhs <= QCD_MAX_RHS) with the
+ * operator loaded in the context, each exactly as qcd_solve (same stopping
+ * test, reliable updates and final FP64 residual), run together: the
+ * right-hand sides are interleaved site by site in the library's fields, so
+ * each link and clover block is read once per site for all of them.  This
+ * is the multi-source workload of the paper's application (section 1), whose
+ * kernels are bound by memory bandwidth (section 4).  Internally n_rhs is
+ * rounded up to a power of two with zero right-hand sides, which converge at
+ * once.  b_dev, x_dev: complex128 [n_rhs][V][4][3], not overlapping.  stats:
+ * NULL or n_rhs entries; iters and reliable_updates count the joint
+ * iterations (the largest over the right-hand sides), seconds the whole call,
+ * flops each right-hand side's share, bytes the call's algorithmic bytes over
+ * n_rhs.  The first call with a given n_rhs allocates the interleaved work
+ * vectors (about 12 x n_rhs' spinor fields, n_rhs' = the rounded count); they
+ * are kept for later calls with as many or fewer right-hand sides.
+ * QCD_ENOCONV if any right-hand side missed tol (all x are written). */
+int qcd_solve_multi(qcd_ctx *ctx, const qcd_solver_params *params, int n_rhs, const void *b_dev, void *x_dev,
+                    qcd_solver_stats *stats);
+
 /* Pseudofermion action and its gauge derivative.
  * S = phi^dag (Mhat^dag Mhat)^{-1} phi with phi_dev complex128 [Vh][4][3] on
  * even sites.  Writes *S; G_dev (complex128 [V][4][3][3]) receives

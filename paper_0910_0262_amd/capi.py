@@ -72,6 +72,7 @@ SIGNATURES = {
     "qcd_get_clover": ([_P, _P, _P], _I),
     "qcd_apply": ([_P, _I, _I, _P, _P], _I),
     "qcd_solve": ([_P, ctypes.POINTER(SolverParams), _P, _P, ctypes.POINTER(SolverStats)], _I),
+    "qcd_solve_multi": ([_P, ctypes.POINTER(SolverParams), _I, _P, _P, ctypes.POINTER(SolverStats)], _I),
     "qcd_action_force": ([_P, ctypes.POINTER(SolverParams), _P, ctypes.POINTER(_D), _P, _P, _P,
                           ctypes.POINTER(SolverStats)], _I),
     "qcd_hmd_step": ([_P, _D, _P, _P, _P, ctypes.POINTER(SolverParams), ctypes.POINTER(_D),
@@ -195,6 +196,23 @@ def qcd_solve(ctx, params: SolverParams, b: torch.Tensor, x: torch.Tensor, volum
     if rc != QCD_OK and (raise_on_noconv or rc != QCD_ENOCONV):
         check(rc)
     return rc, st.as_dict()
+
+
+QCD_MAX_RHS = 16
+
+
+def qcd_solve_multi(ctx, params: SolverParams, b: torch.Tensor, x: torch.Tensor, volume: int,
+                    raise_on_noconv: bool = True) -> tuple[int, list]:
+    """b, x: complex128 (n, ..., V sites, 4, 3) with n <= 16 right-hand sides; returns (status, [stats] * n)."""
+    n = b.shape[0]
+    if not 1 <= n <= QCD_MAX_RHS:
+        raise ValueError(f"1 <= n_rhs <= {QCD_MAX_RHS} required, got {n}")
+    st = (SolverStats * n)()
+    rc = lib().qcd_solve_multi(ctx, ctypes.byref(params), n, _ptr(b, torch.complex128, n * volume * 12, "b"),
+                               _ptr(x, torch.complex128, n * volume * 12, "x"), st)
+    if rc != QCD_OK and (raise_on_noconv or rc != QCD_ENOCONV):
+        check(rc)
+    return rc, [st[k].as_dict() for k in range(n)]
 
 
 def qcd_action_force(ctx, params: SolverParams, phi: torch.Tensor, G: torch.Tensor, F: torch.Tensor | None,

@@ -46,6 +46,25 @@ constexpr int kRing = 64;
 
 }  // namespace
 
+// Solver work set: vectors, partial sums and CG states for nr = 1 << lg
+// right-hand sides interleaved site by site (element (cb << lg) | r).  The
+// context's single-source set (lg = 0) also serves the operators, the force
+// and the trajectory; a second set is allocated for multi-source solves.
+struct Work {
+  int lg = 0, nr = 1;
+  Geom gv;  // Vh and stride of all right-hand sides together (for the BLAS kernels)
+  double2* vec[NSLOT] = {};
+  uint4* hv[NHSLOT] = {};
+  float* hs[NHSLOT] = {};
+  float4* x32 = nullptr;
+  double* partial = nullptr;
+  CgState* st = nullptr;         // nr states
+  CgState* st_host = nullptr;    // pinned copy of the last states read (nr)
+  CgState* mbox_host = nullptr;  // host-mapped rings of posted states: [nr][kRing]
+  CgState* mbox_dev = nullptr;   // device address of mbox_host
+  int post_ctr = 0;              // host mirror of CgState::post_seq (equal for all nr states)
+};
+
 struct qcd_ctx {
   int dims[4];
   Geom g;
@@ -71,19 +90,11 @@ struct qcd_ctx {
   float2* clovh_es = nullptr;
   uint4* clovinvh_o = nullptr;
   float2* clovinvh_os = nullptr;
-  double2* vec[NSLOT] = {};
-  uint4* hv[NHSLOT] = {};
-  float* hs[NHSLOT] = {};
-  float4* x32 = nullptr;
-  double* partial = nullptr;
-  int n_partial = 0;
-
-  CgState* st = nullptr;
-  CgState* st_host = nullptr;  // pinned
-  CgState* mbox_host = nullptr;  // host-mapped ring of posted states
-  CgState* mbox_dev = nullptr;   // device address of mbox_host
+  Work w1;          // single source (operators, solve, force, trajectory)
+  Work wm;          // multi-source solves
+  Work* w = &w1;    // the set the solver drivers use
+  int wm_lg_alloc = -1;  // right-hand sides (log2) wm was allocated for
   hipEvent_t ev[kRing] = {};
-  int post_ctr = 0;             // host mirror of CgState::post_seq
   hipStream_t cap = nullptr;    // private stream used only to capture graphs
   hipGraphExec_t iter_graph[2] = {nullptr, nullptr};  // one CG iteration: [FP64, mixed]
   int* status = nullptr;
@@ -95,11 +106,11 @@ struct qcd_ctx {
 
   // 64-thread workgroups measured fastest for the stencils at 32^3x64
   int block() const { return block_opt ? block_opt : 64; }
-  SpF64 f64(int s) const { return SpF64{vec[s], g.stride}; }
-  SpRef ref64(int s) const { return SpRef{SP_F64, vec[s], nullptr}; }
-  SpRef refh(int s) const { return SpRef{SP_H, hv[s], hs[s]}; }
-  SpH h(int s) const { return SpH{hv[s], hs[s], g.stride}; }
-  SpF32 f32() const { return SpF32{x32, g.stride}; }
+  SpF64 f64(int s) const { return SpF64{w->vec[s], w->gv.stride}; }
+  SpRef ref64(int s) const { return SpRef{SP_F64, w->vec[s], nullptr}; }
+  SpRef refh(int s) const { return SpRef{SP_H, w->hv[s], w->hs[s]}; }
+  SpH h(int s) const { return SpH{w->hv[s], w->hs[s], w->gv.stride}; }
+  SpF32 f32() const { return SpF32{w->x32, w->gv.stride}; }
   const void* links64() const { return link_recon == 12 ? (const void*)u12 : (const void*)u18; }
   int lk64() const { return link_recon == 12 ? LK_F64_12 : LK_F64_18; }
   const double2* clov_par(int par) const { return clov + (size_t)par * 36 * g.stride; }
@@ -113,6 +124,71 @@ int dalloc(T** p, size_t bytes) {
     *p = nullptr;
     return fail(QCD_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
   }
+  return QCD_OK;
+}
+
+void free_work(Work& w) {
+  auto f = [](void* p) {
+    if (p) (void)hipFree(p);
+  };
+  for (auto*& p : w.vec) f(p), p = nullptr;
+  for (auto*& p : w.hv) f(p), p = nullptr;
+  for (auto*& p : w.hs) f(p), p = nullptr;
+  f(w.x32);
+  f(w.partial);
+  f(w.st);
+  if (w.st_host) (void)hipHostFree(w.st_host);
+  if (w.mbox_host) (void)hipHostFree(w.mbox_host);
+  w = Work();
+}
+
+// Allocate a work set for 1 << lg right-hand sides; with all_slots the
+// vectors of the operators and the force too, otherwise the solver's only.
+int alloc_work(const Geom& g, Work& w, int lg, bool all_slots) {
+  w.lg = lg;
+  w.nr = 1 << lg;
+  w.gv = g;
+  w.gv.Vh = g.Vh << lg;
+  w.gv.stride = g.stride << lg;
+  const size_t S = (size_t)w.gv.stride;
+  int rc = QCD_OK;
+  auto A = [&](auto** p, size_t bytes) {
+    if (rc == QCD_OK) rc = dalloc(p, bytes);
+  };
+  static const int solver_slots[] = {V_T, V_Q, V_X, V_R, V_P, V_RHS, V_B_E, V_B_O, V_AUX, V_OUT_O};
+  static const int solver_hslots[] = {H_P, H_T, H_Q, H_R};
+  if (all_slots) {
+    for (int k = 0; k < NSLOT; ++k) A(&w.vec[k], 12 * S * sizeof(double2));
+    for (int k = 0; k < NHSLOT; ++k) {
+      A(&w.hv[k], 3 * S * sizeof(uint4));
+      A(&w.hs[k], S * sizeof(float));
+    }
+  } else {
+    for (int k : solver_slots) A(&w.vec[k], 12 * S * sizeof(double2));
+    for (int k : solver_hslots) {
+      A(&w.hv[k], 3 * S * sizeof(uint4));
+      A(&w.hs[k], S * sizeof(float));
+    }
+  }
+  A(&w.x32, 6 * S * sizeof(float4));
+  // partial sums: one per workgroup of 64 threads (the smallest block) per right-hand side
+  A(&w.partial, ((size_t)blocks_for(w.gv.Vh, 64) + 64) * w.nr * sizeof(double));
+  A(&w.st, w.nr * sizeof(CgState));
+  if (rc == QCD_OK && hipHostMalloc((void**)&w.st_host, w.nr * sizeof(CgState), hipHostMallocDefault) != hipSuccess)
+    rc = fail(QCD_ENOMEM, "pinned host allocation failed");
+  if (rc == QCD_OK && hipHostMalloc((void**)&w.mbox_host, (size_t)w.nr * kRing * sizeof(CgState),
+                                    hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess)
+    rc = fail(QCD_ENOMEM, "pinned host allocation failed");
+  if (rc == QCD_OK && hipHostGetDevicePointer((void**)&w.mbox_dev, w.mbox_host, 0) != hipSuccess)
+    rc = fail(QCD_EHIP, "hipHostGetDevicePointer failed");
+  if (rc == QCD_OK && hipMemset(w.st, 0, w.nr * sizeof(CgState)) != hipSuccess) rc = fail(QCD_EHIP, "hipMemset failed");
+  if (rc != QCD_OK) {
+    free_work(w);
+    return rc;
+  }
+  std::memset(w.st_host, 0, w.nr * sizeof(CgState));
+  std::memset(w.mbox_host, 0, (size_t)w.nr * kRing * sizeof(CgState));
+  w.post_ctr = 0;
   return QCD_OK;
 }
 
@@ -131,21 +207,14 @@ void free_ctx(qcd_ctx* c) {
   f(c->clovh_es);
   f(c->clovinvh_o);
   f(c->clovinvh_os);
-  for (auto* p : c->vec) f(p);
-  for (auto* p : c->hv) f(p);
-  for (auto* p : c->hs) f(p);
-  f(c->x32);
-  f(c->partial);
-
-  f(c->st);
+  free_work(c->w1);
+  free_work(c->wm);
   f(c->status);
   f(c->xi);
   f(c->gint);
   f(c->fbuf);
   f(c->logdet);
-  if (c->st_host) (void)hipHostFree(c->st_host);
   if (c->status_host) (void)hipHostFree(c->status_host);
-  if (c->mbox_host) (void)hipHostFree(c->mbox_host);
   for (auto& gx : c->iter_graph)
     if (gx) (void)hipGraphExecDestroy(gx);
   if (c->cap) (void)hipStreamDestroy(c->cap);
@@ -176,7 +245,8 @@ DslashOp base_op(const qcd_ctx* c, int par_out) {
   op.link_kind = c->lk64();
   op.links = c->links64();
   op.c = 1.0;
-  op.partial = c->partial;
+  op.partial = c->w->partial;
+  op.lg = c->w->lg;
   return op;
 }
 
@@ -269,31 +339,41 @@ int m_parity(qcd_ctx* c, int par, int in_site, int in_nbr, int out, bool dag, in
   return QCD_OK;
 }
 
-int nblocks(const qcd_ctx* c) { return blocks_for(c->g.Vh, c->block()); }
+int nblocks(const qcd_ctx* c) { return blocks_for(c->w->gv.Vh, c->block()); }
 
 int sync_state(qcd_ctx* c) {
-  HIPCHK(hipMemcpyAsync(c->st_host, c->st, sizeof(CgState), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipMemcpyAsync(c->w->st_host, c->w->st, c->w->nr * sizeof(CgState), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
   return QCD_OK;
 }
 
 // |x|^2 of an FP64 vector into st->scalar and returned (synchronises)
 int norm2_sync(qcd_ctx* c, int s, double* out) {
-  HIPCHK(launch_norm2(c->g, c->ref64(s), c->partial, c->block(), c->stream));
-  HIPCHK(launch_fin_scalar(c->st, c->partial, nblocks(c), c->stream));
+  HIPCHK(launch_norm2(c->w->gv, c->w->lg, c->ref64(s), c->w->partial, c->block(), c->stream));
+  HIPCHK(launch_fin_scalar(c->w->st, c->w->partial, nblocks(c), c->w->nr, c->stream));
   QCHK(sync_state(c));
-  *out = c->st_host->scalar;
+  *out = c->w->st_host->scalar;
   return QCD_OK;
 }
 
-// bytes of one Mhat^dag Mhat per even site (k1 + k2, twice), algorithmic
-double mdagm_bytes_per_site(const qcd_ctx* c, bool mixed) {
+// |x|^2 of each right-hand side of an FP64 vector (synchronises)
+int norm2_each(qcd_ctx* c, int s, double* out) {
+  HIPCHK(launch_norm2(c->w->gv, c->w->lg, c->ref64(s), c->w->partial, c->block(), c->stream));
+  HIPCHK(launch_fin_scalar(c->w->st, c->w->partial, nblocks(c), c->w->nr, c->stream));
+  QCHK(sync_state(c));
+  for (int r = 0; r < c->w->nr; ++r) out[r] = c->w->st_host[r].scalar;
+  return QCD_OK;
+}
+
+// algorithmic bytes of one Mhat^dag Mhat per even site (k1 + k2, twice) for
+// nr interleaved right-hand sides: spinors nr times, links and clover once
+double mdagm_bytes_per_site(const qcd_ctx* c, bool mixed, int nr = 1) {
   if (!mixed) {
-    const double sp = 192.0, lk = (c->link_recon == 12 ? 96.0 : 144.0), cl = 576.0;
+    const double sp = 192.0 * nr, lk = (c->link_recon == 12 ? 96.0 : 144.0), cl = 576.0;
     const double k1 = sp + 8 * lk + cl + sp, k2 = k1 + sp;
     return 2.0 * (k1 + k2);
   }
-  const double sp = 52.0, lk = 24.0, cl = (c->mixed_clover == 16 ? 152.0 : 288.0);
+  const double sp = 52.0 * nr, lk = 24.0, cl = (c->mixed_clover == 16 ? 152.0 : 288.0);
   const double k1 = sp + 8 * lk + cl + sp, k2 = k1 + sp;
   return 2.0 * (k1 + k2);
 }
@@ -319,15 +399,38 @@ struct Pipe {
 
 // slot of the next posted state; mirrors post() on the device
 int next_slot(qcd_ctx* c) {
-  const int s = c->post_ctr % kRing;
-  c->post_ctr = (c->post_ctr + 1) % (kRing * 1024);
+  const int s = c->w->post_ctr % kRing;
+  c->w->post_ctr = (c->w->post_ctr + 1) % (kRing * 1024);
   return s;
 }
 
-// read the state posted in `slot` once the work before event `slot` has completed
+// Read the states posted in `slot` once the work before event `slot` has
+// completed: into the work set's host copies, and combined into `out`.  With
+// several right-hand sides `out` is done / halted when all are, non-finite or
+// asking for a reliable update when any is; its rr_hi is the largest
+// rr_hi / stop2 over the right-hand sides still running (stop2 = 1).
 int wait_slot(qcd_ctx* c, int slot, CgState* out) {
   HIPCHK(hipEventSynchronize(c->ev[slot]));
-  std::memcpy(out, (const void*)&c->mbox_host[slot], sizeof(CgState));
+  Work& w = *c->w;
+  for (int r = 0; r < w.nr; ++r)
+    std::memcpy(&w.st_host[r], (const void*)&w.mbox_host[(size_t)r * kRing + slot], sizeof(CgState));
+  *out = w.st_host[0];
+  if (w.nr == 1) return QCD_OK;
+  double worst = 0.0;
+  for (int r = 0; r < w.nr; ++r) {
+    const CgState& q = w.st_host[r];
+    if (r > 0) {
+      out->done &= q.done;
+      out->halt &= q.halt;
+      out->nan |= q.nan;
+      out->need_ru |= q.need_ru;
+      out->iter = std::max(out->iter, q.iter);
+      out->ru_count = std::max(out->ru_count, q.ru_count);
+    }
+    if (!q.done && q.stop2 > 0.0) worst = std::max(worst, q.rr_hi / q.stop2);
+  }
+  out->rr_hi = worst;
+  out->stop2 = 1.0;
   return QCD_OK;
 }
 
@@ -344,16 +447,16 @@ int residual_f64(qcd_ctx* c, int x, int out_r, const CgState* st) {
 int recompute_residual(qcd_ctx* c, int restart, CgState* posted) {
   QCHK(residual_f64(c, V_X, V_R, nullptr));
   const int slot = next_slot(c);
-  HIPCHK(launch_fin_ru(c->st, c->partial, nblocks(c), restart, c->mbox_dev, kRing, c->stream));
+  HIPCHK(launch_fin_ru(c->w->st, c->w->partial, nblocks(c), c->w->nr, restart, c->w->mbox_dev, kRing, c->stream));
   HIPCHK(hipEventRecord(c->ev[slot], c->stream));
   if (posted) QCHK(wait_slot(c, slot, posted));
   return QCD_OK;
 }
 
 int init_recurrence(qcd_ctx* c, double tol, double delta, int max_iter, int mixed, CgState* posted) {
-  HIPCHK(launch_norm2(c->g, c->ref64(V_RHS), c->partial, c->block(), c->stream));
+  HIPCHK(launch_norm2(c->w->gv, c->w->lg, c->ref64(V_RHS), c->w->partial, c->block(), c->stream));
   const int slot = next_slot(c);
-  HIPCHK(launch_fin_init(c->st, c->partial, nblocks(c), tol, delta, max_iter, mixed, c->mbox_dev, kRing, c->stream));
+  HIPCHK(launch_fin_init(c->w->st, c->w->partial, nblocks(c), c->w->nr, tol, delta, max_iter, mixed, c->w->mbox_dev, kRing, c->stream));
   HIPCHK(hipEventRecord(c->ev[slot], c->stream));
   return wait_slot(c, slot, posted);
 }
@@ -367,21 +470,21 @@ int launch_iter(qcd_ctx* c, bool mixed) {
   // device-scope fence per workgroup, which writes back the XCD's L2 on this
   // GPU and made the iteration three times slower.)
   if (!mixed) {
-    QCHK(k1_f64(c, V_P, V_T, false, c->st));
-    QCHK(k2_f64(c, V_P, V_T, V_Q, false, 1, 0, 0.0, false, c->st));
-    HIPCHK(launch_fin_alpha(c->st, c->partial, nb, c->stream));
-    QCHK(k1_f64(c, V_Q, V_T, true, c->st));
-    QCHK(k2_f64(c, V_Q, V_T, V_R, true, 2, V_R, 0.0, true, c->st));
-    HIPCHK(launch_fin_beta(c->st, c->partial, nb, c->mbox_dev, kRing, c->stream));
-    HIPCHK(launch_xp_update_f64(c->g, c->st, c->f64(V_X), c->f64(V_P), c->f64(V_R), c->block(), c->stream));
+    QCHK(k1_f64(c, V_P, V_T, false, c->w->st));
+    QCHK(k2_f64(c, V_P, V_T, V_Q, false, 1, 0, 0.0, false, c->w->st));
+    HIPCHK(launch_fin_alpha(c->w->st, c->w->partial, nb, c->w->nr, c->stream));
+    QCHK(k1_f64(c, V_Q, V_T, true, c->w->st));
+    QCHK(k2_f64(c, V_Q, V_T, V_R, true, 2, V_R, 0.0, true, c->w->st));
+    HIPCHK(launch_fin_beta(c->w->st, c->w->partial, nb, c->w->nr, c->w->mbox_dev, kRing, c->stream));
+    HIPCHK(launch_xp_update_f64(c->w->gv, c->w->lg, c->w->st, c->f64(V_X), c->f64(V_P), c->f64(V_R), c->block(), c->stream));
   } else {
-    QCHK(k1_h(c, H_P, H_T, false, c->st));
-    QCHK(k2_h(c, H_P, H_T, H_Q, false, 1, 0, false, c->st));
-    HIPCHK(launch_fin_alpha(c->st, c->partial, nb, c->stream));
-    QCHK(k1_h(c, H_Q, H_T, true, c->st));
-    QCHK(k2_h(c, H_Q, H_T, H_R, true, 2, H_R, true, c->st));
-    HIPCHK(launch_fin_beta(c->st, c->partial, nb, c->mbox_dev, kRing, c->stream));
-    HIPCHK(launch_xp_update_h(c->g, c->st, c->f32(), c->h(H_P), c->h(H_R), c->block(), c->stream));
+    QCHK(k1_h(c, H_P, H_T, false, c->w->st));
+    QCHK(k2_h(c, H_P, H_T, H_Q, false, 1, 0, false, c->w->st));
+    HIPCHK(launch_fin_alpha(c->w->st, c->w->partial, nb, c->w->nr, c->stream));
+    QCHK(k1_h(c, H_Q, H_T, true, c->w->st));
+    QCHK(k2_h(c, H_Q, H_T, H_R, true, 2, H_R, true, c->w->st));
+    HIPCHK(launch_fin_beta(c->w->st, c->w->partial, nb, c->w->nr, c->w->mbox_dev, kRing, c->stream));
+    HIPCHK(launch_xp_update_h(c->w->gv, c->w->lg, c->w->st, c->f32(), c->h(H_P), c->h(H_R), c->block(), c->stream));
   }
   return QCD_OK;
 }
@@ -419,7 +522,7 @@ int capture_iter(qcd_ctx* c, bool mixed) {
 }
 
 int enqueue_iter(qcd_ctx* c, Pipe& pp, bool mixed) {
-  if (c->use_graph) {
+  if (c->use_graph && c->w->lg == 0) {
     QCHK(capture_iter(c, mixed));
     HIPCHK(hipGraphLaunch(c->iter_graph[mixed ? 1 : 0], c->stream));
   } else {
@@ -446,11 +549,11 @@ int cg_fp64(qcd_ctx* c, const qcd_solver_params* p, bool use_x0, CgCounters& cnt
     QCHK(recompute_residual(c, 1, &s));
     cnt.mdagm += 1;
     if (s.nan) return fail(QCD_ENAN, "non-finite residual of the starting guess");
-    HIPCHK(launch_p_restart_f64(g, c->st, c->f64(V_P), c->f64(V_R), B, c->stream));
+    HIPCHK(launch_p_restart_f64(c->w->gv, c->w->lg, c->w->st, c->f64(V_P), c->f64(V_R), B, c->stream));
   } else {
-    HIPCHK(launch_zero(g, c->ref64(V_X), B, c->stream));
-    HIPCHK(launch_convert(g, c->ref64(V_RHS), c->ref64(V_R), B, c->stream));
-    HIPCHK(launch_convert(g, c->ref64(V_RHS), c->ref64(V_P), B, c->stream));
+    HIPCHK(launch_zero(c->w->gv, c->ref64(V_X), B, c->stream));
+    HIPCHK(launch_convert(c->w->gv, c->ref64(V_RHS), c->ref64(V_R), B, c->stream));
+    HIPCHK(launch_convert(c->w->gv, c->ref64(V_RHS), c->ref64(V_P), B, c->stream));
   }
   const int depth = pipeline_depth(p);
   int restarts = 0;
@@ -468,15 +571,14 @@ int cg_fp64(qcd_ctx* c, const qcd_solver_params* p, bool use_x0, CgCounters& cnt
     if (s.nan) return fail(QCD_ENAN, "non-finite residual in FP64 CG");
     if (s.done || restarts >= 8) break;
     ++restarts;
-    HIPCHK(launch_p_restart_f64(g, c->st, c->f64(V_P), c->f64(V_R), B, c->stream));
+    HIPCHK(launch_p_restart_f64(c->w->gv, c->w->lg, c->w->st, c->f64(V_P), c->f64(V_R), B, c->stream));
     pp = Pipe();
   }
   HIPCHK(hipStreamSynchronize(c->stream));
-  *c->st_host = s;
   cnt.iters += s.iter;
   cnt.mdagm += s.iter;
   cnt.restarts += restarts;
-  cnt.blas_bytes += (double)s.iter * 7.0 * 192.0 * g.Vh;
+  cnt.blas_bytes += (double)s.iter * 7.0 * 192.0 * c->w->gv.Vh;
   return QCD_OK;
 }
 
@@ -491,10 +593,10 @@ int cg_mixed(qcd_ctx* c, const qcd_solver_params* p, CgCounters& cnt) {
   CgState s;
   QCHK(init_recurrence(c, p->tol, p->delta_reliable, p->max_iter, 1, &s));
   if (s.nan) return fail(QCD_ENAN, "non-finite right-hand side");
-  HIPCHK(launch_zero(g, c->ref64(V_X), B, c->stream));
-  HIPCHK(launch_zero(g, SpRef{SP_F32, c->x32, nullptr}, B, c->stream));
-  HIPCHK(launch_convert(g, c->ref64(V_RHS), c->refh(H_R), B, c->stream));
-  HIPCHK(launch_convert(g, c->ref64(V_RHS), c->refh(H_P), B, c->stream));
+  HIPCHK(launch_zero(c->w->gv, c->ref64(V_X), B, c->stream));
+  HIPCHK(launch_zero(c->w->gv, SpRef{SP_F32, c->w->x32, nullptr}, B, c->stream));
+  HIPCHK(launch_convert(c->w->gv, c->ref64(V_RHS), c->refh(H_R), B, c->stream));
+  HIPCHK(launch_convert(c->w->gv, c->ref64(V_RHS), c->refh(H_P), B, c->stream));
   const int depth = pipeline_depth(p);
   Pipe pp;
   long long ru_barrier = 0;  // iterations enqueued before the last reliable update
@@ -514,7 +616,7 @@ int cg_mixed(qcd_ctx* c, const qcd_solver_params* p, CgCounters& cnt) {
         stall = 0;
       } else if (++stall >= 3) {
         HIPCHK(hipStreamSynchronize(c->stream));
-        HIPCHK(launch_ru_accum(g, c->f64(V_X), c->f32(), B, c->stream));
+        HIPCHK(launch_ru_accum(c->w->gv, c->f64(V_X), c->f32(), B, c->stream));
         cnt.iters += s.iter;
         cnt.mdagm_mixed += s.iter;
         cnt.restarts += 1;
@@ -525,19 +627,18 @@ int cg_mixed(qcd_ctx* c, const qcd_solver_params* p, CgCounters& cnt) {
     }
     if (s.need_ru && idx >= ru_barrier) {
       // fold x_lo into x_hi, r = rhs - A x_hi in FP64, re-encode r; p is kept
-      HIPCHK(launch_ru_accum(g, c->f64(V_X), c->f32(), B, c->stream));
+      HIPCHK(launch_ru_accum(c->w->gv, c->f64(V_X), c->f32(), B, c->stream));
       QCHK(recompute_residual(c, 0, nullptr));
-      HIPCHK(launch_convert(g, c->ref64(V_R), c->refh(H_R), B, c->stream));
+      HIPCHK(launch_convert(c->w->gv, c->ref64(V_R), c->refh(H_R), B, c->stream));
       cnt.mdagm += 1;
       cnt.ru += 1;
       ru_barrier = pp.seq;
     }
   }
   HIPCHK(hipStreamSynchronize(c->stream));
-  *c->st_host = s;
   cnt.iters += s.iter;
   cnt.mdagm_mixed += s.iter;
-  cnt.blas_bytes += (double)s.iter * (2 * 52.0 + 3 * 52.0 + 2 * 96.0) * g.Vh;
+  cnt.blas_bytes += (double)s.iter * (2 * 52.0 + 3 * 52.0 + 2 * 96.0) * c->w->gv.Vh;
   return QCD_OK;
 }
 
@@ -557,10 +658,9 @@ int validate_params(const qcd_solver_params* p) {
   return QCD_OK;
 }
 
-void fill_stats(qcd_ctx* c, const CgCounters& cnt, const qcd_solver_params* p, double seconds, double true_rel,
-                qcd_solver_stats* out) {
+void fill_stats_from(qcd_ctx* c, const CgState& s, const CgCounters& cnt, const qcd_solver_params* p,
+                     double seconds, double true_rel, qcd_solver_stats* out, int n_share = 1) {
   if (!out) return;
-  const CgState& s = *c->st_host;
   out->iters = cnt.iters;
   out->reliable_updates = cnt.ru;
   out->restarts = cnt.restarts;
@@ -569,10 +669,16 @@ void fill_stats(qcd_ctx* c, const CgCounters& cnt, const qcd_solver_params* p, d
   out->true_rel_res = true_rel;
   out->seconds = seconds;
   const double mdagm = cnt.mdagm + cnt.mdagm_mixed;
+  const int nr = c->w->nr;
   out->flops = mdagm * 2.0 * 1824.0 * c->g.V;
-  out->bytes = (cnt.mdagm * mdagm_bytes_per_site(c, false) + cnt.mdagm_mixed * mdagm_bytes_per_site(c, true)) *
-                   c->g.Vh +
-               cnt.blas_bytes;
+  out->bytes = ((cnt.mdagm * mdagm_bytes_per_site(c, false, nr) + cnt.mdagm_mixed * mdagm_bytes_per_site(c, true, nr)) *
+                    c->g.Vh +
+                cnt.blas_bytes) /
+               n_share;
+}
+void fill_stats(qcd_ctx* c, const CgCounters& cnt, const qcd_solver_params* p, double seconds, double true_rel,
+                qcd_solver_stats* out) {
+  fill_stats_from(c, *c->w->st_host, cnt, p, seconds, true_rel, out);
 }
 
 // Solve on even sites for a prepared right-hand side in V_RHS; result in V_X.
@@ -641,40 +747,20 @@ int qcd_create(const int dims[4], int device, uintptr_t hip_stream, qcd_ctx** ou
   A(&c->clovh_es, S * sizeof(float2));
   A(&c->clovinvh_o, 9 * S * sizeof(uint4));
   A(&c->clovinvh_os, S * sizeof(float2));
-  for (int k = 0; k < NSLOT; ++k) A(&c->vec[k], 12 * S * sizeof(double2));
-  for (int k = 0; k < NHSLOT; ++k) {
-    A(&c->hv[k], 3 * S * sizeof(uint4));
-    A(&c->hs[k], S * sizeof(float));
-  }
-  A(&c->x32, 6 * S * sizeof(float4));
   A(&c->logdet, S * sizeof(double));
-  c->n_partial = g.Vh / 64 + 64;
-  A(&c->partial, (size_t)c->n_partial * sizeof(double));
-
-  A(&c->st, sizeof(CgState));
   A(&c->status, sizeof(int));
-  if (rc == QCD_OK && hipHostMalloc((void**)&c->st_host, sizeof(CgState), hipHostMallocDefault) != hipSuccess)
-    rc = fail(QCD_ENOMEM, "pinned host allocation failed");
+  if (rc == QCD_OK) rc = alloc_work(g, c->w1, 0, true);
   if (rc == QCD_OK && hipHostMalloc((void**)&c->status_host, sizeof(int), hipHostMallocDefault) != hipSuccess)
     rc = fail(QCD_ENOMEM, "pinned host allocation failed");
-  if (rc == QCD_OK &&
-      hipHostMalloc((void**)&c->mbox_host, kRing * sizeof(CgState), hipHostMallocMapped | hipHostMallocCoherent) !=
-          hipSuccess)
-    rc = fail(QCD_ENOMEM, "pinned host allocation failed");
-  if (rc == QCD_OK && hipHostGetDevicePointer((void**)&c->mbox_dev, c->mbox_host, 0) != hipSuccess)
-    rc = fail(QCD_EHIP, "hipHostGetDevicePointer failed");
   for (int k = 0; k < kRing && rc == QCD_OK; ++k)
     if (hipEventCreateWithFlags(&c->ev[k], hipEventDisableTiming) != hipSuccess) rc = fail(QCD_EHIP, "hipEventCreate failed");
   if (rc == QCD_OK && hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) != hipSuccess)
     rc = fail(QCD_EHIP, "hipStreamCreate failed");
-  if (rc == QCD_OK && hipMemset(c->st, 0, sizeof(CgState)) != hipSuccess) rc = fail(QCD_EHIP, "hipMemset failed");
   if (rc != QCD_OK) {
     free_ctx(c);
     delete c;
     return rc;
   }
-  std::memset(c->st_host, 0, sizeof(CgState));
-  std::memset(c->mbox_host, 0, kRing * sizeof(CgState));
   *out = c;
   return QCD_OK;
 }
@@ -820,7 +906,7 @@ int qcd_apply(qcd_ctx* c, int op, int prec, const void* in_dev, void* out_dev) {
     HIPCHK(launch_unpack_spinor_cb(g, c->f64(cur), (double2*)out_dev, c->stream));
     return QCD_OK;
   }
-  HIPCHK(launch_convert(g, c->ref64(V_IN_E), c->refh(H_IN), c->block(), c->stream));
+  HIPCHK(launch_convert(c->w->gv, c->ref64(V_IN_E), c->refh(H_IN), c->block(), c->stream));
   int cur = H_IN;
   if (first) {
     QCHK(k1_h(c, cur, H_T, false, nullptr));
@@ -833,22 +919,30 @@ int qcd_apply(qcd_ctx* c, int op, int prec, const void* in_dev, void* out_dev) {
     QCHK(k2_h(c, cur, H_T, dst, true, 0, 0, false, nullptr));
     cur = dst;
   }
-  HIPCHK(launch_convert(g, c->refh(cur), c->ref64(V_OUT_E), c->block(), c->stream));
+  HIPCHK(launch_convert(c->w->gv, c->refh(cur), c->ref64(V_OUT_E), c->block(), c->stream));
   HIPCHK(launch_unpack_spinor_cb(g, c->f64(V_OUT_E), (double2*)out_dev, c->stream));
   return QCD_OK;
 }
 
-int qcd_solve(qcd_ctx* c, const qcd_solver_params* p, const void* b_dev, void* x_dev, qcd_solver_stats* stats) {
-  QCHK(check_ctx(c));
-  QCHK(validate_params(p));
-  if (!b_dev || !x_dev) return fail(QCD_EINVAL, "null vector pointer");
-  QCHK(need_clover(c));
-  const auto t0 = std::chrono::steady_clock::now();
+}  // extern "C"
+
+namespace {
+
+// Selects the work set the drivers use for the lifetime of the guard.
+struct WorkGuard {
+  qcd_ctx* c;
+  WorkGuard(qcd_ctx* ctx, Work* w) : c(ctx) { c->w = w; }
+  ~WorkGuard() { c->w = &c->w1; }
+};
+
+// Solve M x = b for the work set's right-hand sides (n of them, packed by the
+// caller into V_B_E / V_B_O); writes x into V_X / V_OUT_O and the stats.
+int solve_packed(qcd_ctx* c, const qcd_solver_params* p, int n, qcd_solver_stats* stats,
+                 std::chrono::steady_clock::time_point t0) {
   const Geom& g = c->g;
-  const int B = c->block(), nb = nblocks(c);
-  // b -> (b_e, b_o); bhat = b_e + kappa H_eo A_oo^{-1} b_o; rhs = Mhat^dag bhat
-  HIPCHK(launch_pack_spinor_full(g, (const double2*)b_dev, c->f64(V_B_E), c->f64(V_B_O), c->stream));
-  HIPCHK(launch_clover_apply(g, c->f64(V_B_O), c->f64(V_T), c->clov_inv, c->stream));
+  const int B = c->block(), nb = nblocks(c), nr = c->w->nr;
+  // bhat = b_e + kappa H_eo A_oo^{-1} b_o; rhs = Mhat^dag bhat
+  HIPCHK(launch_clover_apply(g, c->w->lg, c->f64(V_B_O), c->f64(V_T), c->clov_inv, c->stream));
   {
     DslashOp op = base_op(c, 0);
     op.in = c->ref64(V_T);
@@ -863,7 +957,8 @@ int qcd_solve(qcd_ctx* c, const qcd_solver_params* p, const void* b_dev, void* x
   CgCounters cnt;
   int rc = solve_even(c, p, cnt);
   if (rc != QCD_OK && rc != QCD_ENOCONV) return rc;
-  CgState s_end = *c->st_host;
+  CgState s_end[16];
+  std::memcpy(s_end, c->w->st_host, nr * sizeof(CgState));
   // x_o = A_oo^{-1} (b_o + kappa H_oe x_e)
   {
     DslashOp op = base_op(c, 1);
@@ -876,26 +971,84 @@ int qcd_solve(qcd_ctx* c, const qcd_solver_params* p, const void* b_dev, void* x
     op.c = c->kappa;
     HIPCHK(launch_dslash(g, op, B, c->stream));
   }
-  HIPCHK(launch_unpack_spinor_full(g, c->f64(V_X), c->f64(V_OUT_O), (double2*)x_dev, c->stream));
-  // true residual ||b - M x|| / ||b|| on the full lattice
-  double rn = 0.0, bn = 0.0, t;
+  // true residual ||b - M x|| / ||b|| on the full lattice, per right-hand side
+  double rn[16] = {}, bn[16] = {}, t[16];
   QCHK(m_parity(c, 0, V_X, V_OUT_O, V_AUX, false, 2, V_B_E, -1.0));
-  HIPCHK(launch_fin_scalar(c->st, c->partial, nb, c->stream));
+  HIPCHK(launch_fin_scalar(c->w->st, c->w->partial, nb, nr, c->stream));
   QCHK(sync_state(c));
-  rn += c->st_host->scalar;
+  for (int r = 0; r < nr; ++r) rn[r] += c->w->st_host[r].scalar;
   QCHK(m_parity(c, 1, V_OUT_O, V_X, V_AUX, false, 2, V_B_O, -1.0));
-  HIPCHK(launch_fin_scalar(c->st, c->partial, nb, c->stream));
+  HIPCHK(launch_fin_scalar(c->w->st, c->w->partial, nb, nr, c->stream));
   QCHK(sync_state(c));
-  rn += c->st_host->scalar;
-  QCHK(norm2_sync(c, V_B_E, &t));
-  bn += t;
-  QCHK(norm2_sync(c, V_B_O, &t));
-  bn += t;
+  for (int r = 0; r < nr; ++r) rn[r] += c->w->st_host[r].scalar;
+  QCHK(norm2_each(c, V_B_E, t));
+  for (int r = 0; r < nr; ++r) bn[r] += t[r];
+  QCHK(norm2_each(c, V_B_O, t));
+  for (int r = 0; r < nr; ++r) bn[r] += t[r];
   const double seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-  *c->st_host = s_end;
-  fill_stats(c, cnt, p, seconds, bn > 0 ? std::sqrt(rn / bn) : 0.0, stats);
-  if (s_end.rr_hi > s_end.stop2) return fail(QCD_ENOCONV, "solver reached max_iter without meeting tol");
+  std::memcpy(c->w->st_host, s_end, nr * sizeof(CgState));
+  bool all_conv = true;
+  for (int r = 0; r < n; ++r) {
+    if (stats) fill_stats_from(c, s_end[r], cnt, p, seconds, bn[r] > 0 ? std::sqrt(rn[r] / bn[r]) : 0.0, &stats[r], n);
+    if (s_end[r].rr_hi > s_end[r].stop2) all_conv = false;
+  }
+  if (!all_conv) return fail(QCD_ENOCONV, "solver reached max_iter without meeting tol");
   return QCD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int qcd_solve(qcd_ctx* c, const qcd_solver_params* p, const void* b_dev, void* x_dev, qcd_solver_stats* stats) {
+  QCHK(check_ctx(c));
+  QCHK(validate_params(p));
+  if (!b_dev || !x_dev) return fail(QCD_EINVAL, "null vector pointer");
+  QCHK(need_clover(c));
+  const auto t0 = std::chrono::steady_clock::now();
+  WorkGuard wg(c, &c->w1);
+  HIPCHK(launch_pack_spinor_full(c->g, (const double2*)b_dev, c->f64(V_B_E), c->f64(V_B_O), c->stream));
+  const int rc = solve_packed(c, p, 1, stats, t0);
+  if (rc != QCD_OK && rc != QCD_ENOCONV) return rc;
+  HIPCHK(launch_unpack_spinor_full(c->g, c->f64(V_X), c->f64(V_OUT_O), (double2*)x_dev, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return rc;
+}
+
+int qcd_solve_multi(qcd_ctx* c, const qcd_solver_params* p, int n_rhs, const void* b_dev, void* x_dev,
+                    qcd_solver_stats* stats) {
+  QCHK(check_ctx(c));
+  QCHK(validate_params(p));
+  if (!b_dev || !x_dev) return fail(QCD_EINVAL, "null vector pointer");
+  if (n_rhs < 1 || n_rhs > QCD_MAX_RHS) return fail(QCD_EINVAL, "n_rhs must lie in [1, 16]");
+  if (b_dev == x_dev) return fail(QCD_EINVAL, "b and x must not overlap");
+  QCHK(need_clover(c));
+  const auto t0 = std::chrono::steady_clock::now();
+  int lg = 0;
+  while ((1 << lg) < n_rhs) ++lg;
+  // a set allocated for more right-hand sides serves fewer (its buffers are larger)
+  if (c->wm.st == nullptr || c->wm_lg_alloc < lg) {
+    free_work(c->wm);
+    c->wm_lg_alloc = -1;
+    QCHK(alloc_work(c->g, c->wm, lg, false));
+    c->wm_lg_alloc = lg;
+  }
+  Work& w = c->wm;
+  w.lg = lg;
+  w.nr = 1 << lg;
+  w.gv = c->g;
+  w.gv.Vh = c->g.Vh << lg;
+  w.gv.stride = c->g.stride << lg;
+  // every state posts in step from zero
+  HIPCHK(hipMemsetAsync(w.st, 0, ((size_t)1 << c->wm_lg_alloc) * sizeof(CgState), c->stream));
+  w.post_ctr = 0;
+  WorkGuard wg(c, &w);
+  HIPCHK(launch_pack_spinor_multi(c->g, lg, n_rhs, (const double2*)b_dev, c->f64(V_B_E), c->f64(V_B_O), c->stream));
+  const int rc = solve_packed(c, p, n_rhs, stats, t0);
+  if (rc != QCD_OK && rc != QCD_ENOCONV) return rc;
+  HIPCHK(launch_unpack_spinor_multi(c->g, lg, n_rhs, c->f64(V_X), c->f64(V_OUT_O), (double2*)x_dev, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return rc;
 }
 
 // Force pipeline on the current context state; phi in V_RHS (even sites).
@@ -910,14 +1063,14 @@ static int force_core(qcd_ctx* c, const qcd_solver_params* p, double* S, CgCount
   // keep phi: the solver overwrites work slots but not V_RHS
   int rc = run_cg(c, p, cnt);
   if (rc != QCD_OK) return rc;
-  *conv_rc = c->st_host->rr_hi <= c->st_host->stop2 ? QCD_OK : QCD_ENOCONV;
-  CgState s_end = *c->st_host;
+  *conv_rc = c->w->st_host->rr_hi <= c->w->st_host->stop2 ? QCD_OK : QCD_ENOCONV;
+  CgState s_end = *c->w->st_host;
   // S = Re phi^dag X
-  HIPCHK(launch_dot_re(g, c->f64(V_RHS), c->f64(V_X), c->partial, c->block(), c->stream));
-  HIPCHK(launch_fin_scalar(c->st, c->partial, nb, c->stream));
+  HIPCHK(launch_dot_re(c->w->gv, c->w->lg, c->f64(V_RHS), c->f64(V_X), c->w->partial, c->block(), c->stream));
+  HIPCHK(launch_fin_scalar(c->w->st, c->w->partial, nb, c->w->nr, c->stream));
   QCHK(sync_state(c));
-  if (S) *S = c->st_host->scalar;
-  *c->st_host = s_end;
+  if (S) *S = c->w->st_host->scalar;
+  *c->w->st_host = s_end;
   // Z = A_oo^{-1} H_oe X; Y = Mhat X; W = A_oo^{-1} g5 H_oe g5 Y
   QCHK(k1_f64(c, V_X, V_Z, false, nullptr));
   QCHK(k2_f64(c, V_X, V_Z, V_Y, false, 0, 0, 0.0, false, nullptr));
@@ -1000,19 +1153,19 @@ int qcd_hmd_step(qcd_ctx* c, double dt, void* U_dev, double* P_dev, const void* 
 
 // beta sum (1 - Re tr P / 3) (synchronises; overwrites the host state mirror)
 static int gauge_action_sync(qcd_ctx* c, double beta, double* S) {
-  HIPCHK(launch_plaquette(c->g, c->u18, c->partial, c->block(), c->stream));
-  HIPCHK(launch_fin_scalar(c->st, c->partial, nblocks(c), c->stream));
+  HIPCHK(launch_plaquette(c->g, c->u18, c->w->partial, c->block(), c->stream));
+  HIPCHK(launch_fin_scalar(c->w->st, c->w->partial, nblocks(c), c->w->nr, c->stream));
   QCHK(sync_state(c));
-  *S = beta * c->st_host->scalar;
+  *S = beta * c->w->st_host->scalar;
   return QCD_OK;
 }
 
 // -2 sum_odd ln det A from the last inversion (synchronises)
 static int det_action_sync(qcd_ctx* c, double* S) {
-  HIPCHK(launch_sum_cb(c->g, c->logdet, c->partial, c->block(), c->stream));
-  HIPCHK(launch_fin_scalar(c->st, c->partial, nblocks(c), c->stream));
+  HIPCHK(launch_sum_cb(c->g, c->logdet, c->w->partial, c->block(), c->stream));
+  HIPCHK(launch_fin_scalar(c->w->st, c->w->partial, nblocks(c), c->w->nr, c->stream));
   QCHK(sync_state(c));
-  *S = -2.0 * c->st_host->scalar;
+  *S = -2.0 * c->w->st_host->scalar;
   return QCD_OK;
 }
 

@@ -45,6 +45,45 @@ __global__ void unpack_spinor_cb_k(int n, SpF64 f, double2* __restrict__ user) {
   for (int k = 0; k < 12; ++k) user[(size_t)i * 12 + k] = f.p[(size_t)k * f.stride + i];
 }
 
+// n right-hand sides [n][V][12] -> interleaved fields, element (cb << lg) | r;
+// one thread per (site, rhs slot), slots r >= n are zero.
+__global__ void pack_spinor_multi_k(Geom g, int lg, int n, const double2* __restrict__ user, SpF64 e, SpF64 o) {
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ((size_t)g.V << lg)) return;
+  const int r = (int)(t & ((1u << lg) - 1)), i = (int)(t >> lg);
+  int x[4];
+  lex_coords(i, g, x);
+  const SpF64 f = parity_of(x) ? o : e;
+  const size_t v = ((size_t)(i >> 1) << lg) | r;
+#pragma unroll
+  for (int k = 0; k < 12; ++k)
+    f.p[(size_t)k * f.stride + v] = r < n ? user[((size_t)r * g.V + i) * 12 + k] : make_double2(0.0, 0.0);
+}
+__global__ void unpack_spinor_multi_k(Geom g, int lg, int n, SpF64 e, SpF64 o, double2* __restrict__ user) {
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ((size_t)g.V << lg)) return;
+  const int r = (int)(t & ((1u << lg) - 1)), i = (int)(t >> lg);
+  if (r >= n) return;
+  int x[4];
+  lex_coords(i, g, x);
+  const SpF64 f = parity_of(x) ? o : e;
+  const size_t v = ((size_t)(i >> 1) << lg) | r;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) user[((size_t)r * g.V + i) * 12 + k] = f.p[(size_t)k * f.stride + v];
+}
+hipError_t launch_pack_spinor_multi(const Geom& g, int lg, int n, const double2* user, SpF64 e, SpF64 o,
+                                    hipStream_t s) {
+  const size_t nt = (size_t)g.V << lg;
+  hipLaunchKernelGGL(pack_spinor_multi_k, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s, g, lg, n, user, e, o);
+  return hipGetLastError();
+}
+hipError_t launch_unpack_spinor_multi(const Geom& g, int lg, int n, SpF64 e, SpF64 o, double2* user, hipStream_t s) {
+  const size_t nt = (size_t)g.V << lg;
+  hipLaunchKernelGGL(unpack_spinor_multi_k, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s, g, lg, n, e, o,
+                     user);
+  return hipGetLastError();
+}
+
 hipError_t launch_pack_spinor_full(const Geom& g, const double2* user, SpF64 e, SpF64 o, hipStream_t s) {
   hipLaunchKernelGGL(pack_spinor_full_k, dim3(blocks_for(g.V, 256)), dim3(256), 0, s, g, user, e, o);
   return hipGetLastError();
@@ -165,45 +204,46 @@ hipError_t launch_unpack_clover(const Geom& g, const double2* clov, double2* use
 }
 
 // ------------------------------------------------------------------ reductions
+// gv: Vh and stride of all interleaved right-hand sides together.
 template <class F>
-__global__ void __launch_bounds__(256) norm2_k(Geom g, F x, double* partial) {
+__global__ void __launch_bounds__(256) norm2_k(Geom gv, int lg, F x, double* partial) {
   const int blk = xcd_block(blockIdx.x, gridDim.x);
   const int i = blk * blockDim.x + threadIdx.x;
   double n = 0.0;
-  if (i < g.Vh) {
+  if (i < gv.Vh) {
     Spinor<double> v;
     load(x, i, v);
     n = site_norm2(v);
   }
-  block_sum_store(n, partial, blk);
+  block_sum_store_seg(n, partial, blk, gridDim.x, lg);
 }
-__global__ void __launch_bounds__(256) dot_re_k(Geom g, SpF64 a, SpF64 b, double* partial) {
+__global__ void __launch_bounds__(256) dot_re_k(Geom gv, int lg, SpF64 a, SpF64 b, double* partial) {
   const int blk = xcd_block(blockIdx.x, gridDim.x);
   const int i = blk * blockDim.x + threadIdx.x;
   double n = 0.0;
-  if (i < g.Vh) {
+  if (i < gv.Vh) {
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
       const double2 u = a.p[(size_t)k * a.stride + i], v = b.p[(size_t)k * b.stride + i];
       n += u.x * v.x + u.y * v.y;
     }
   }
-  block_sum_store(n, partial, blk);
+  block_sum_store_seg(n, partial, blk, gridDim.x, lg);
 }
-hipError_t launch_norm2(const Geom& g, SpRef x, double* partial, int block, hipStream_t s) {
-  const int nb = blocks_for(g.Vh, block);
+hipError_t launch_norm2(const Geom& gv, int lg, SpRef x, double* partial, int block, hipStream_t s) {
+  const int nb = blocks_for(gv.Vh, block);
   if (x.kind == SP_F64)
-    hipLaunchKernelGGL(norm2_k<SpF64>, dim3(nb), dim3(block), 0, s, g, SpF64{(double2*)x.p, g.stride}, partial);
+    hipLaunchKernelGGL(norm2_k<SpF64>, dim3(nb), dim3(block), 0, s, gv, lg, SpF64{(double2*)x.p, gv.stride}, partial);
   else if (x.kind == SP_F32)
-    hipLaunchKernelGGL(norm2_k<SpF32>, dim3(nb), dim3(block), 0, s, g, SpF32{(float4*)x.p, g.stride}, partial);
+    hipLaunchKernelGGL(norm2_k<SpF32>, dim3(nb), dim3(block), 0, s, gv, lg, SpF32{(float4*)x.p, gv.stride}, partial);
   else if (x.kind == SP_H)
-    hipLaunchKernelGGL(norm2_k<SpH>, dim3(nb), dim3(block), 0, s, g, SpH{(uint4*)x.p, x.s, g.stride}, partial);
+    hipLaunchKernelGGL(norm2_k<SpH>, dim3(nb), dim3(block), 0, s, gv, lg, SpH{(uint4*)x.p, x.s, gv.stride}, partial);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
 }
-hipError_t launch_dot_re(const Geom& g, SpF64 a, SpF64 b, double* partial, int block, hipStream_t s) {
-  hipLaunchKernelGGL(dot_re_k, dim3(blocks_for(g.Vh, block)), dim3(block), 0, s, g, a, b, partial);
+hipError_t launch_dot_re(const Geom& gv, int lg, SpF64 a, SpF64 b, double* partial, int block, hipStream_t s) {
+  hipLaunchKernelGGL(dot_re_k, dim3(blocks_for(gv.Vh, block)), dim3(block), 0, s, gv, lg, a, b, partial);
   return hipGetLastError();
 }
 
@@ -213,12 +253,19 @@ hipError_t launch_dot_re(const Geom& g, SpF64 a, SpF64 b, double* partial, int b
 // iteration's event has completed) and advances post_seq; the host counts
 // the posting launches it issues, so it knows the slot of each without
 // passing it as an argument (the same captured graph serves every iteration).
+// Workgroup r of a launch handles right-hand side r: its state st[r], its
+// partials partial[r * n ...], its mailbox ring mbox[r * ring ...].
 __global__ void fin_scalar_k(CgState* st, const double* partial, int n) {
+  st += blockIdx.x;
+  partial += (size_t)blockIdx.x * n;
   const double s = block_sum_partials(partial, n);
   if (threadIdx.x == 0) st->scalar = s;
 }
 __global__ void fin_init_k(CgState* st, const double* partial, int n, double tol, double delta, int max_iter,
                            int mixed, CgState* mbox, int ring) {
+  st += blockIdx.x;
+  partial += (size_t)blockIdx.x * n;
+  mbox += (size_t)blockIdx.x * ring;
   const double rr = block_sum_partials(partial, n);
   if (threadIdx.x != 0) return;
   st->rr = rr;
@@ -243,11 +290,16 @@ __global__ void fin_init_k(CgState* st, const double* partial, int n, double tol
   post(st, mbox, ring);
 }
 __global__ void fin_alpha_k(CgState* st, const double* partial, int n) {
+  st += blockIdx.x;
+  partial += (size_t)blockIdx.x * n;
   if (st->halt) return;
   const double qq = block_sum_partials(partial, n);
   if (threadIdx.x == 0) state_alpha(st, qq);
 }
 __global__ void fin_beta_k(CgState* st, const double* partial, int n, CgState* mbox, int ring) {
+  st += blockIdx.x;
+  partial += (size_t)blockIdx.x * n;
+  mbox += (size_t)blockIdx.x * ring;
   if (st->halt) {
     if (threadIdx.x == 0) state_halted(st, mbox, ring);
     return;
@@ -259,6 +311,9 @@ __global__ void fin_beta_k(CgState* st, const double* partial, int n, CgState* m
 //   restart = 0 (reliable update): r replaces the recurrence residual, p is kept;
 //   restart = 1 (CG restart): beta = 0, so the following p update sets p = r.
 __global__ void fin_ru_k(CgState* st, const double* partial, int n, int restart, CgState* mbox, int ring) {
+  st += blockIdx.x;
+  partial += (size_t)blockIdx.x * n;
+  mbox += (size_t)blockIdx.x * ring;
   const double rr = block_sum_partials(partial, n);
   if (threadIdx.x != 0) return;
   st->rr_hi = rr;
@@ -282,33 +337,37 @@ __global__ void fin_ru_k(CgState* st, const double* partial, int n, int restart,
   post(st, mbox, ring);
 }
 
-#define FIN_LAUNCH(kernel, ...)                                     \
-  hipLaunchKernelGGL(kernel, dim3(1), dim3(1024), 0, s, __VA_ARGS__); \
+#define FIN_LAUNCH(kernel, ...)                                      \
+  hipLaunchKernelGGL(kernel, dim3(nr), dim3(1024), 0, s, __VA_ARGS__); \
   return hipGetLastError();
 
-hipError_t launch_fin_scalar(CgState* st, const double* partial, int n, hipStream_t s) {
+hipError_t launch_fin_scalar(CgState* st, const double* partial, int n, int nr, hipStream_t s) {
   FIN_LAUNCH(fin_scalar_k, st, partial, n)
 }
-hipError_t launch_fin_init(CgState* st, const double* partial, int n, double tol, double delta, int max_iter,
+hipError_t launch_fin_init(CgState* st, const double* partial, int n, int nr, double tol, double delta, int max_iter,
                            int mixed, CgState* mbox, int ring, hipStream_t s) {
   FIN_LAUNCH(fin_init_k, st, partial, n, tol, delta, max_iter, mixed, mbox, ring)
 }
-hipError_t launch_fin_alpha(CgState* st, const double* partial, int n, hipStream_t s) {
+hipError_t launch_fin_alpha(CgState* st, const double* partial, int n, int nr, hipStream_t s) {
   FIN_LAUNCH(fin_alpha_k, st, partial, n)
 }
-hipError_t launch_fin_beta(CgState* st, const double* partial, int n, CgState* mbox, int ring, hipStream_t s) {
+hipError_t launch_fin_beta(CgState* st, const double* partial, int n, int nr, CgState* mbox, int ring,
+                           hipStream_t s) {
   FIN_LAUNCH(fin_beta_k, st, partial, n, mbox, ring)
 }
-hipError_t launch_fin_ru(CgState* st, const double* partial, int n, int restart, CgState* mbox, int ring,
+hipError_t launch_fin_ru(CgState* st, const double* partial, int n, int nr, int restart, CgState* mbox, int ring,
                          hipStream_t s) {
   FIN_LAUNCH(fin_ru_k, st, partial, n, restart, mbox, ring)
 }
 
 // ------------------------------------------------------------------ CG vector updates
 // x += alpha p; then p = r + beta p unless the recurrence stopped.
-__global__ void __launch_bounds__(256) xp_update_f64_k(Geom g, const CgState* st, SpF64 x, SpF64 p, SpF64 r) {
-  if (!st->do_x) return;
+// Element i belongs to right-hand side i & ((1 << lg) - 1) and uses its state.
+__global__ void __launch_bounds__(256) xp_update_f64_k(Geom g, int lg, const CgState* st, SpF64 x, SpF64 p,
+                                                       SpF64 r) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  st += i & ((1 << lg) - 1);
+  if (!st->do_x) return;
   if (i >= g.Vh) return;
   const double al = st->alpha, be = st->beta;
   const bool dp = st->do_p;
@@ -326,9 +385,10 @@ __global__ void __launch_bounds__(256) xp_update_f64_k(Geom g, const CgState* st
     }
   }
 }
-__global__ void __launch_bounds__(256) p_restart_f64_k(Geom g, const CgState* st, SpF64 p, SpF64 r) {
-  if (!st->do_p) return;
+__global__ void __launch_bounds__(256) p_restart_f64_k(Geom g, int lg, const CgState* st, SpF64 p, SpF64 r) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  st += i & ((1 << lg) - 1);
+  if (!st->do_p) return;
   if (i >= g.Vh) return;
   const double be = st->beta;
 #pragma unroll
@@ -344,9 +404,10 @@ __global__ void __launch_bounds__(256) p_restart_f64_k(Geom g, const CgState* st
   }
 }
 // mixed: x (FP32) += alpha p (binary16); p = r + beta p, re-encoded.
-__global__ void __launch_bounds__(256) xp_update_h_k(Geom g, const CgState* st, SpF32 x, SpH p, SpH r) {
-  if (!st->do_x) return;
+__global__ void __launch_bounds__(256) xp_update_h_k(Geom g, int lg, const CgState* st, SpF32 x, SpH p, SpH r) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  st += i & ((1 << lg) - 1);
+  if (!st->do_x) return;
   if (i >= g.Vh) return;
   const float al = float(st->alpha), be = float(st->beta);
   Spinor<float> pv, xv;
@@ -384,17 +445,19 @@ __global__ void __launch_bounds__(256) ru_accum_k(Geom g, SpF64 xhi, SpF32 xlo) 
   store(xlo, i, z);
 }
 
-hipError_t launch_xp_update_f64(const Geom& g, const CgState* st, SpF64 x, SpF64 p, SpF64 r, int block,
+hipError_t launch_xp_update_f64(const Geom& gv, int lg, const CgState* st, SpF64 x, SpF64 p, SpF64 r, int block,
                                 hipStream_t s) {
-  hipLaunchKernelGGL(xp_update_f64_k, dim3(blocks_for(g.Vh, block)), dim3(block), 0, s, g, st, x, p, r);
+  hipLaunchKernelGGL(xp_update_f64_k, dim3(blocks_for(gv.Vh, block)), dim3(block), 0, s, gv, lg, st, x, p, r);
   return hipGetLastError();
 }
-hipError_t launch_p_restart_f64(const Geom& g, const CgState* st, SpF64 p, SpF64 r, int block, hipStream_t s) {
-  hipLaunchKernelGGL(p_restart_f64_k, dim3(blocks_for(g.Vh, block)), dim3(block), 0, s, g, st, p, r);
+hipError_t launch_p_restart_f64(const Geom& gv, int lg, const CgState* st, SpF64 p, SpF64 r, int block,
+                                hipStream_t s) {
+  hipLaunchKernelGGL(p_restart_f64_k, dim3(blocks_for(gv.Vh, block)), dim3(block), 0, s, gv, lg, st, p, r);
   return hipGetLastError();
 }
-hipError_t launch_xp_update_h(const Geom& g, const CgState* st, SpF32 x, SpH p, SpH r, int block, hipStream_t s) {
-  hipLaunchKernelGGL(xp_update_h_k, dim3(blocks_for(g.Vh, block)), dim3(block), 0, s, g, st, x, p, r);
+hipError_t launch_xp_update_h(const Geom& gv, int lg, const CgState* st, SpF32 x, SpH p, SpH r, int block,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(xp_update_h_k, dim3(blocks_for(gv.Vh, block)), dim3(block), 0, s, gv, lg, st, x, p, r);
   return hipGetLastError();
 }
 hipError_t launch_ru_accum(const Geom& g, SpF64 xhi, SpF32 xlo, int block, hipStream_t s) {

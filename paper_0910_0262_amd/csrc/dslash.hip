@@ -38,6 +38,7 @@ struct DArgs {
   int g5in, g5out;
   const CgState* st;
   double* partial;
+  int lg;  // log2 of the number of interleaved right-hand sides (MULTI kernels)
 };
 
 // One direction mu: the forward hop (1 - gamma_mu) U_mu(x) psi(x + mu) and
@@ -46,8 +47,10 @@ struct DArgs {
 // the antiperiodic-time sign and a binary16 field's per-site scale multiply
 // the projected half spinor once.  No branch may split this block: with a
 // branch the FP64 kernel runs out of registers and spills.
-template <int MU, bool G5IN, typename R, class A>
-__device__ __forceinline__ void hop_dir(const A& a, int i, const int x[4], Spinor<R>& acc) {
+// i: checkerboard site (links, clover); r: right-hand side (MULTI: spinor
+// element (cb << lg) | r, otherwise cb).
+template <int MU, bool G5IN, bool MULTI, typename R, class A>
+__device__ __forceinline__ void hop_dir(const A& a, int i, int r, const int x[4], Spinor<R>& acc) {
   using SIn = decltype(a.in);
   constexpr bool scaled = SpinorScale<SIn>::scaled;
   const Geom& g = a.g;
@@ -56,11 +59,12 @@ __device__ __forceinline__ void hop_dir(const A& a, int i, const int x[4], Spino
   const int nf = lex(y, g) >> 1;
   y[MU] = (x[MU] == 0 ? g.X[MU] : x[MU]) - 1;
   const int nb = lex(y, g) >> 1;
+  const int ef = MULTI ? ((nf << a.lg) | r) : nf, eb = MULTI ? ((nb << a.lg) | r) : nb;
   Spinor<R> pf, pb;
   Mat<R> uf, ub;
-  load_raw(a.in, nf, pf);
+  load_raw(a.in, ef, pf);
   load_link(a.U, MU, a.par_out, i, uf);
-  load_raw(a.in, nb, pb);
+  load_raw(a.in, eb, pb);
   load_link(a.U, MU, 1 - a.par_out, nb, ub);
   if constexpr (G5IN) {
     neg_lower(pf);
@@ -68,8 +72,8 @@ __device__ __forceinline__ void hop_dir(const A& a, int i, const int x[4], Spino
   }
   R sf = R(1), sb = R(1);
   if constexpr (scaled) {
-    sf = R(scale_of(a.in, nf));
-    sb = R(scale_of(a.in, nb));
+    sf = R(scale_of(a.in, ef));
+    sb = R(scale_of(a.in, eb));
   }
   if constexpr (MU == 3) {
     sf = (g.tb < 0 && x[3] == g.X[3] - 1) ? -sf : sf;
@@ -96,21 +100,27 @@ __device__ __forceinline__ void hop_dir(const A& a, int i, const int x[4], Spino
   accumulate<MU, +1>(acc, uh);
 }
 
-template <typename R, int SITE, bool POST, bool G5IN, class A>
+// MULTI: one work-item per (site, right-hand side) with the right-hand side
+// fastest, so the 1 << lg work-items of a site share its link and clover
+// loads; halted right-hand sides keep computing with alpha = 0 (the grid
+// cannot return early for some of them).
+template <typename R, int SITE, bool POST, bool G5IN, bool MULTI, class A>
 __global__ void __launch_bounds__(256) dslash_kernel(A a) {
-  if (a.st != nullptr && a.st->halt) return;  // uniform over the grid
+  if (!MULTI && a.st != nullptr && a.st->halt) return;  // uniform over the grid
   const int blk = xcd_block(blockIdx.x, gridDim.x);
-  const int i = blk * blockDim.x + threadIdx.x;
+  const int e = blk * blockDim.x + threadIdx.x;  // spinor element
+  const int i = MULTI ? (e >> a.lg) : e;         // checkerboard site
+  const int r = MULTI ? (e & ((1 << a.lg) - 1)) : 0;
   double nrm = 0.0;
   if (i < a.g.Vh) {
     int x[4];
     cb_coords(i, a.par_out, a.g, x);
     Spinor<R> acc;
     zero(acc);
-    hop_dir<0, G5IN>(a, i, x, acc);
-    hop_dir<1, G5IN>(a, i, x, acc);
-    hop_dir<2, G5IN>(a, i, x, acc);
-    hop_dir<3, G5IN>(a, i, x, acc);
+    hop_dir<0, G5IN, MULTI>(a, i, r, x, acc);
+    hop_dir<1, G5IN, MULTI>(a, i, r, x, acc);
+    hop_dir<2, G5IN, MULTI>(a, i, r, x, acc);
+    hop_dir<3, G5IN, MULTI>(a, i, r, x, acc);
     // hop scale, with gamma5 on the output folded into the lower spins
     const R c = R(a.c), cl = a.g5out ? R(-a.c) : R(a.c);
 #pragma unroll
@@ -122,7 +132,7 @@ __global__ void __launch_bounds__(256) dslash_kernel(A a) {
     }
     if constexpr (SITE != 0) {
       Spinor<R> sv;
-      load_once(a.site, i, sv);
+      load_once(a.site, e, sv);
       if constexpr (SITE == 2) apply_clover(a.cpre, i, sv);
 #pragma unroll
       for (int s = 0; s < 4; ++s)
@@ -132,20 +142,29 @@ __global__ void __launch_bounds__(256) dslash_kernel(A a) {
     if constexpr (POST) apply_clover(a.cpost, i, acc);
     if (a.epi == 2) {
       Spinor<R> yv;
-      load_once(a.y, i, yv);
-      const R al = a.a_from_state ? R(-a.st->alpha) : R(a.a);
+      load_once(a.y, e, yv);
+      R al;
+      if constexpr (MULTI)
+        al = a.a_from_state ? (a.st[r].halt ? R(0) : R(-a.st[r].alpha)) : R(a.a);
+      else
+        al = a.a_from_state ? R(-a.st->alpha) : R(a.a);
 #pragma unroll
       for (int s = 0; s < 4; ++s)
 #pragma unroll
         for (int k = 0; k < 3; ++k) yv.v[s][k] = yv.v[s][k] + al * acc.v[s][k];
-      store(a.out, i, yv);
+      store(a.out, e, yv);
       nrm = site_norm2(yv);
     } else {
-      store(a.out, i, acc);
+      store(a.out, e, acc);
       if (a.epi == 1) nrm = site_norm2(acc);
     }
   }
-  if (a.epi >= 1) block_sum_store(nrm, a.partial, blk);
+  if (a.epi >= 1) {
+    if constexpr (MULTI)
+      block_sum_store_seg(nrm, a.partial, blk, gridDim.x, a.lg);
+    else
+      block_sum_store(nrm, a.partial, blk);
+  }
 }
 
 // ------------------------------------------------------------------ dispatch
@@ -184,12 +203,13 @@ template <typename R, class SIn, class SSite, class SOut, class LK, class CPre, 
           bool G5IN>
 static hipError_t run_g5(const Geom& g, const DslashOp& op, int block, hipStream_t s) {
   DArgs<SIn, SSite, SOut, LK, CPre, CPost> a;
+  const int ss = g.stride << op.lg;  // spinor stride: all right-hand sides
   a.g = g;
   a.par_out = op.par_out;
-  a.in = sp_of<SIn>(op.in, g.stride);
-  a.site = sp_of<SSite>(op.site, g.stride);
-  a.out = sp_of<SOut>(op.out, g.stride);
-  a.y = op.epi == 2 ? sp_of<SOut>(op.y, g.stride) : a.out;
+  a.in = sp_of<SIn>(op.in, ss);
+  a.site = sp_of<SSite>(op.site, ss);
+  a.out = sp_of<SOut>(op.out, ss);
+  a.y = op.epi == 2 ? sp_of<SOut>(op.y, ss) : a.out;
   a.U = lk_of<LK>(op.links, g.stride);
   a.cpre = cl_of<CPre>(op.cpre, g.stride);
   a.cpost = cl_of<CPost>(op.cpost, g.stride);
@@ -201,8 +221,12 @@ static hipError_t run_g5(const Geom& g, const DslashOp& op, int block, hipStream
   a.g5out = op.g5out;
   a.st = op.st;
   a.partial = op.partial;
-  const int nb = blocks_for(g.Vh, block);
-  hipLaunchKernelGGL((dslash_kernel<R, SITE, POST, G5IN, decltype(a)>), dim3(nb), dim3(block), 0, s, a);
+  a.lg = op.lg;
+  const int nb = blocks_for(g.Vh << op.lg, block);
+  if (op.lg > 0)
+    hipLaunchKernelGGL((dslash_kernel<R, SITE, POST, G5IN, true, decltype(a)>), dim3(nb), dim3(block), 0, s, a);
+  else
+    hipLaunchKernelGGL((dslash_kernel<R, SITE, POST, G5IN, false, decltype(a)>), dim3(nb), dim3(block), 0, s, a);
   return hipGetLastError();
 }
 
@@ -250,17 +274,18 @@ hipError_t launch_dslash(const Geom& g, const DslashOp& op, int block, hipStream
 }
 
 // ------------------------------------------------------------------ clover only
-__global__ void __launch_bounds__(256) clover_apply_kernel(Geom g, SpF64 in, SpF64 out, CloverF64 c) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= g.Vh) return;
+// element e = (cb << lg) | r
+__global__ void __launch_bounds__(256) clover_apply_kernel(Geom g, int lg, SpF64 in, SpF64 out, CloverF64 c) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (g.Vh << lg)) return;
   Spinor<double> v;
-  load(in, i, v);
-  apply_clover(c, i, v);
-  store(out, i, v);
+  load(in, e, v);
+  apply_clover(c, e >> lg, v);
+  store(out, e, v);
 }
 
-hipError_t launch_clover_apply(const Geom& g, SpF64 in, SpF64 out, const double2* clov, hipStream_t s) {
-  hipLaunchKernelGGL(clover_apply_kernel, dim3(blocks_for(g.Vh, 256)), dim3(256), 0, s, g, in, out,
+hipError_t launch_clover_apply(const Geom& g, int lg, SpF64 in, SpF64 out, const double2* clov, hipStream_t s) {
+  hipLaunchKernelGGL(clover_apply_kernel, dim3(blocks_for(g.Vh << lg, 256)), dim3(256), 0, s, g, lg, in, out,
                      CloverF64{clov, g.stride});
   return hipGetLastError();
 }

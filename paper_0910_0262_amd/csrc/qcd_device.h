@@ -637,6 +637,25 @@ __device__ __forceinline__ void block_sum_store(double v, double* partial, int s
   }
 }
 
+// Segmented version for 1 << lg (<= 16) interleaved right-hand sides: thread
+// t contributes to right-hand side t & ((1 << lg) - 1); the workgroup's sum
+// for right-hand side r goes to partial[r * nblk + slot].  lg = 0 gives the
+// same sums, in the same order, as block_sum_store.
+__device__ __forceinline__ void block_sum_store_seg(double v, double* partial, int slot, int nblk, int lg) {
+  const int nr = 1 << lg;
+  for (int off = 32; off >= nr; off >>= 1) v += __shfl_down(v, off, 64);
+  __shared__ double red[16][16];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane < nr) red[w][lane] = v;
+  __syncthreads();
+  if ((int)threadIdx.x < nr) {
+    double s = 0.0;
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int k = 0; k < nw; ++k) s += red[k][threadIdx.x];
+    partial[(size_t)threadIdx.x * nblk + slot] = s;
+  }
+}
+
 // Fixed-order sum of n partials by one workgroup; the result is returned to
 // every thread.  Deterministic for a given n and blockDim.
 __device__ __forceinline__ double block_sum_partials(const double* p, int n) {

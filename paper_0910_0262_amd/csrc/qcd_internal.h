@@ -125,38 +125,54 @@ struct DslashOp {
   int g5in, g5out;
   const CgState* st;
   double* partial;
+  // Several right-hand sides interleaved site by site: spinor element v =
+  // (cb << lg) | r holds right-hand side r of checkerboard site cb; links and
+  // clover are indexed by cb and shared.  st then points at 1 << lg states
+  // and the partial sums of right-hand side r start at partial[r * blocks].
+  int lg;
 };
 
 inline int blocks_for(int n, int block) { return (n + block - 1) / block; }
 
 // ---- dslash.hip
 hipError_t launch_dslash(const Geom& g, const DslashOp& op, int block, hipStream_t s);
-hipError_t launch_clover_apply(const Geom& g, SpF64 in, SpF64 out, const double2* clov, hipStream_t s);
+hipError_t launch_clover_apply(const Geom& g, int lg, SpF64 in, SpF64 out, const double2* clov, hipStream_t s);
 
 // ---- blas.hip
 hipError_t launch_pack_spinor_full(const Geom& g, const double2* user, SpF64 e, SpF64 o, hipStream_t s);
 hipError_t launch_unpack_spinor_full(const Geom& g, SpF64 e, SpF64 o, double2* user, hipStream_t s);
 hipError_t launch_pack_spinor_cb(const Geom& g, const double2* user, SpF64 f, hipStream_t s);
 hipError_t launch_unpack_spinor_cb(const Geom& g, SpF64 f, double2* user, hipStream_t s);
+// n right-hand sides, caller layout [n][V][4][3] complex128, into the
+// interleaved even / odd fields (rhs slots n .. (1 << lg) - 1 are zero)
+hipError_t launch_pack_spinor_multi(const Geom& g, int lg, int n, const double2* user, SpF64 e, SpF64 o,
+                                    hipStream_t s);
+hipError_t launch_unpack_spinor_multi(const Geom& g, int lg, int n, SpF64 e, SpF64 o, double2* user, hipStream_t s);
 hipError_t launch_pack_gauge(const Geom& g, const double2* user, double2* u18, hipStream_t s);
 hipError_t launch_unpack_gauge(const Geom& g, const double2* u18, double2* user, hipStream_t s);
 hipError_t launch_derive_links(const Geom& g, const double2* u18, double2* u12, uint2* uh, hipStream_t s);
 hipError_t launch_pack_clover(const Geom& g, const double2* user, double2* clov, hipStream_t s);
 hipError_t launch_unpack_clover(const Geom& g, const double2* clov, double2* user, int n_par, int par0,
                                 hipStream_t s);
-hipError_t launch_norm2(const Geom& g, SpRef x, double* partial, int block, hipStream_t s);
-hipError_t launch_dot_re(const Geom& g, SpF64 a, SpF64 b, double* partial, int block, hipStream_t s);
-hipError_t launch_fin_scalar(CgState* st, const double* partial, int n, hipStream_t s);
-hipError_t launch_fin_init(CgState* st, const double* partial, int n, double tol, double delta, int max_iter,
+// Spinor BLAS: gv is the geometry with Vh and stride scaled by the number of
+// right-hand sides (1 << lg); per-rhs states and segmented partial sums.
+hipError_t launch_norm2(const Geom& gv, int lg, SpRef x, double* partial, int block, hipStream_t s);
+hipError_t launch_dot_re(const Geom& gv, int lg, SpF64 a, SpF64 b, double* partial, int block, hipStream_t s);
+// Finalisation kernels: one workgroup per right-hand side (nr of them), each
+// summing its n partials and updating its own state.
+hipError_t launch_fin_scalar(CgState* st, const double* partial, int n, int nr, hipStream_t s);
+hipError_t launch_fin_init(CgState* st, const double* partial, int n, int nr, double tol, double delta, int max_iter,
                            int mixed, CgState* mbox, int ring, hipStream_t s);
-hipError_t launch_fin_alpha(CgState* st, const double* partial, int n, hipStream_t s);
-hipError_t launch_fin_beta(CgState* st, const double* partial, int n, CgState* mbox, int ring, hipStream_t s);
-hipError_t launch_fin_ru(CgState* st, const double* partial, int n, int restart, CgState* mbox, int ring,
+hipError_t launch_fin_alpha(CgState* st, const double* partial, int n, int nr, hipStream_t s);
+hipError_t launch_fin_beta(CgState* st, const double* partial, int n, int nr, CgState* mbox, int ring, hipStream_t s);
+hipError_t launch_fin_ru(CgState* st, const double* partial, int n, int nr, int restart, CgState* mbox, int ring,
                          hipStream_t s);
-hipError_t launch_xp_update_f64(const Geom& g, const CgState* st, SpF64 x, SpF64 p, SpF64 r, int block,
+hipError_t launch_xp_update_f64(const Geom& gv, int lg, const CgState* st, SpF64 x, SpF64 p, SpF64 r, int block,
                                 hipStream_t s);
-hipError_t launch_xp_update_h(const Geom& g, const CgState* st, SpF32 x, SpH p, SpH r, int block, hipStream_t s);
-hipError_t launch_p_restart_f64(const Geom& g, const CgState* st, SpF64 p, SpF64 r, int block, hipStream_t s);
+hipError_t launch_xp_update_h(const Geom& gv, int lg, const CgState* st, SpF32 x, SpH p, SpH r, int block,
+                              hipStream_t s);
+hipError_t launch_p_restart_f64(const Geom& gv, int lg, const CgState* st, SpF64 p, SpF64 r, int block,
+                                hipStream_t s);
 hipError_t launch_ru_accum(const Geom& g, SpF64 xhi, SpF32 xlo, int block, hipStream_t s);
 hipError_t launch_convert(const Geom& g, SpRef src, SpRef dst, int block, hipStream_t s);
 hipError_t launch_zero(const Geom& g, SpRef x, int block, hipStream_t s);

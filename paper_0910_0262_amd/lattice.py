@@ -101,6 +101,17 @@ class Lattice:
         st["status"] = capi.STATUS_NAMES[rc]
         return x, st
 
+    def solve_multi(self, b: torch.Tensor, prec="fp64", tol=1e-10, max_iter=20000, pipeline_depth=2,
+                    delta_reliable=0.1, raise_on_noconv=True):
+        """Solve M x_k = b_k for b of shape (n, Lt, Lz, Ly, Lx, 4, 3), n <= 16, in one interleaved
+        multi-source solve; returns (x, [stats dict] * n)."""
+        x = torch.empty_like(b)
+        p = capi.make_params(_PREC[prec], tol, max_iter, pipeline_depth, delta_reliable)
+        rc, sts = capi.qcd_solve_multi(self._ctx, p, b, x, self.V, raise_on_noconv)
+        for st in sts:
+            st["status"] = capi.STATUS_NAMES[rc]
+        return x, sts
+
     def action_force(self, phi: torch.Tensor, prec="fp64", tol=1e-12, max_iter=20000, pipeline_depth=2,
                      delta_reliable=0.1, want_F=True, want_X=True):
         """S = phi^dag (Mhat^dag Mhat)^{-1} phi and its derivatives.
