@@ -2,11 +2,15 @@
 """Benchmark: CG time-to-solution (mixed vs FP64) and Mhat^dag Mhat bandwidth on one MI355X.
 
 One step is one pass of the hot path over one batch of synthetic input at
-32^3 x 64 (kappa 0.1255, c_sw 1.0, links exp(iH) with H of width 0.2): for
-each of the 8 Gaussian sources a mixed-precision solve and an FP64 solve of
-M x = b to tol 1e-10, then one fermion force with the mixed solve inside,
-then a timed run of the stencil kernels (k1, k2, Mhat^dag Mhat).  All input
-fields are resident in GPU memory before the timed region starts.
+32^3 x 64 (kappa 0.1255, c_sw 1.0, links exp(iH) with H of width 0.2): the 8
+Gaussian sources solved (M x = b to tol 1e-10) together in one mixed-precision
+and one FP64 multi-source solve (sources interleaved site by site, each link
+and clover block read once per site for all of them), one single-source solve
+of each precision for comparison, one fermion force with the mixed solve
+inside, and a timed run of the stencil kernels (k1, k2, Mhat^dag Mhat) for
+one and for 8 sources.  `value` is the mixed time to solution per source:
+the multi-source solve's time over 8.  All input fields are resident in GPU
+memory before the timed region starts.
 
 Prints one JSON line on stdout; progress goes to stderr.
 
@@ -32,7 +36,13 @@ METRIC = "CG time-to-solution + M†M GB/s (% HBM peak), mixed vs FP64, 16^4 & 3
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 FLOPS_PER_SITE = 1824.0  # 1320 hopping + 504 clover per site per M application
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k1_mixed_32x32x32x64.md")
-ROOFLINE_KERNEL = ("dslash_kernel<float, 0, true, false,", "LinkH12", "CloverH>")
+# kernels whose HBM traffic the committed counter summary records: the mixed
+# k1 launch of the multi-source solve (the timed headline) and of the
+# single-source solve
+TRAFFIC_KERNELS = {
+    "k1_mixed_multi": ("dslash_kernel<float, 0, true, false, true,", "LinkH12", "CloverH>"),
+    "k1_mixed_single": ("dslash_kernel<float, 0, true, false, false,", "LinkH12", "CloverH>"),
+}
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_0910_0262_amd", "csrc", f) for f in ("qcd_device.h", "dslash.hip")]
 
 
@@ -63,6 +73,24 @@ def mdagm_bytes_per_site(prec: str, mixed_clover=16) -> float:
     return 2 * (k1_bytes_per_site(prec, mixed_clover=mixed_clover) + k2_bytes_per_site(prec, mixed_clover=mixed_clover))
 
 
+# the same with nr interleaved right-hand sides: spinors nr times, links and clover once
+def spinor_bytes(prec: str) -> float:
+    return 192.0 if prec == "fp64" else 52.0
+
+
+def k1_bytes_multi(prec: str, nr: int, mixed_clover=16) -> float:
+    sp = spinor_bytes(prec)
+    return k1_bytes_per_site(prec, mixed_clover=mixed_clover) + 2 * sp * (nr - 1)
+
+
+def k2_bytes_multi(prec: str, nr: int, mixed_clover=16) -> float:
+    return k1_bytes_multi(prec, nr, mixed_clover) + spinor_bytes(prec) * nr
+
+
+def mdagm_bytes_multi(prec: str, nr: int, mixed_clover=16) -> float:
+    return 2 * (k1_bytes_multi(prec, nr, mixed_clover) + k2_bytes_multi(prec, nr, mixed_clover))
+
+
 def _read_traffic_file():
     with open(TRAFFIC_FILE) as f:
         text = f.read()
@@ -70,19 +98,19 @@ def _read_traffic_file():
     return json.loads(block)
 
 
-def traffic_for(vh: int):
-    """HBM bytes per launch of the roofline kernel from the committed rocprofv3
-    counter summary, if it still describes the current kernel source; else None."""
+def traffic_for(key: str, vh: int):
+    """HBM bytes per launch of a kernel from the committed rocprofv3 counter
+    summary, if it still describes the current kernel source; else None."""
     try:
         t = _read_traffic_file()
     except (OSError, ValueError, IndexError):
         return None
-    if t.get("source_sha256") != kernel_source_hash() or t.get("vh") != vh:
+    if t.get("source_sha256") != kernel_source_hash() or t.get("vh") != vh or key not in t.get("kernels", {}):
         return None
-    return t["traffic_bytes"]
+    return t["kernels"][key]["traffic_bytes"]
 
 
-def traffic_summary(fetch_csv: str, write_csv: str, vh: int, command: str) -> None:
+def traffic_summary(fetch_csv: str, write_csv: str, vh: int, command: str, nr: int = 8) -> None:
     """Write the committed traffic summary from two rocprofv3 --pmc runs
     (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch).  Each counter is scaled by
     what it reads for the 2 GiB copy kernel that bench.py runs (2 GiB read,
@@ -90,33 +118,43 @@ def traffic_summary(fetch_csv: str, write_csv: str, vh: int, command: str) -> No
     left out."""
     import csv
 
-    def per_kernel(path):
-        rows = list(csv.DictReader(open(path)))
-        k = [float(r["Counter_Value"]) for r in rows if all(t in r["Kernel_Name"] for t in ROOFLINE_KERNEL)]
-        c = [float(r["Counter_Value"]) for r in rows if "stream_copy_k" in r["Kernel_Name"]]
+    def rows_of(path):
+        return list(csv.DictReader(open(path)))
+
+    def mean_of(rows, tokens):
+        k = [float(r["Counter_Value"]) for r in rows if all(t in r["Kernel_Name"] for t in tokens)]
         med = float(np.median(k))
         k = [v for v in k if v > 0.5 * med]
-        return float(np.mean(k)), len(k), float(np.mean(c))
+        return float(np.mean(k)), len(k)
 
-    f_k, n_f, f_c = per_kernel(fetch_csv)
-    w_k, n_w, w_c = per_kernel(write_csv)
+    fr, wr = rows_of(fetch_csv), rows_of(write_csv)
+    f_c, _ = mean_of(fr, ("stream_copy_k",))
+    w_c, _ = mean_of(wr, ("stream_copy_k",))
     copy_bytes = float(2 << 30)
     fs, ws = copy_bytes / (f_c * 1024.0), copy_bytes / (w_c * 1024.0)
-    traffic = f_k * 1024.0 * fs + w_k * 1024.0 * ws
-    alg = k1_bytes_per_site("mixed") * vh
-    rec = {"kernel": " ".join(ROOFLINE_KERNEL), "vh": vh, "fetch_kib": f_k, "write_kib": w_k,
-           "dispatches": [n_f, n_w], "copy_fetch_kib": f_c, "copy_write_kib": w_c, "copy_bytes": copy_bytes,
-           "fetch_scale": fs, "write_scale": ws, "traffic_bytes": traffic, "algorithmic_bytes": alg,
-           "traffic_over_algorithmic": traffic / alg, "source_sha256": kernel_source_hash()}
+    alg = {"k1_mixed_multi": k1_bytes_multi("mixed", nr) * vh, "k1_mixed_single": k1_bytes_per_site("mixed") * vh}
+    kernels = {}
+    for key, tokens in TRAFFIC_KERNELS.items():
+        f_k, n_f = mean_of(fr, tokens)
+        w_k, n_w = mean_of(wr, tokens)
+        traffic = f_k * 1024.0 * fs + w_k * 1024.0 * ws
+        kernels[key] = {"kernel": " ".join(tokens), "fetch_kib": f_k, "write_kib": w_k, "dispatches": [n_f, n_w],
+                        "traffic_bytes": traffic, "algorithmic_bytes": alg[key],
+                        "traffic_over_algorithmic": traffic / alg[key]}
+    rec = {"vh": vh, "nr_multi": nr, "copy_fetch_kib": f_c, "copy_write_kib": w_c, "copy_bytes": copy_bytes,
+           "fetch_scale": fs, "write_scale": ws, "kernels": kernels, "source_sha256": kernel_source_hash()}
     with open(TRAFFIC_FILE, "w") as f:
         f.write("# HBM traffic of the mixed k1 stencil at 32x32x32x64 (rocprofv3 counters)\n\n")
         f.write("Two counter passes over the same command, run from the repository root on one MI355X:\n\n")
         f.write("```\n" + command + "\n```\n\n")
         f.write(f"FETCH_SIZE reads {f_c:.0f} KiB and WRITE_SIZE {w_c:.0f} KiB per dispatch of the 2 GiB copy "
-                f"kernel, so they are scaled by {fs:.3f} and {ws:.3f}.  Per launch of the k1 kernel "
-                f"({n_f} dispatches): {traffic / 1e6:.1f} MB of HBM traffic against {alg / 1e6:.1f} MB "
-                f"algorithmic ({traffic / alg:.3f}x).  `source_sha256` is the hash of the kernel sources "
-                f"the counters were taken on; bench.py reports traffic as null once they change.\n\n")
+                f"kernel, so they are scaled by {fs:.3f} and {ws:.3f}.\n\n")
+        f.write("| kernel | dispatches | HBM traffic per launch | algorithmic | ratio |\n|---|---:|---:|---:|---:|\n")
+        for key, k in kernels.items():
+            f.write(f"| {key} (`{k['kernel']}`) | {k['dispatches'][0]} | {k['traffic_bytes'] / 1e6:.1f} MB | "
+                    f"{k['algorithmic_bytes'] / 1e6:.1f} MB | {k['traffic_over_algorithmic']:.3f} |\n")
+        f.write("\n`source_sha256` is the hash of the kernel sources the counters were taken on; bench.py "
+                "reports traffic as null once they change.\n\n")
         f.write("```json\n" + json.dumps(rec, indent=1) + "\n```\n")
     print(json.dumps(rec))
 
@@ -283,20 +321,40 @@ def main() -> int:
     del src, dst
     log(f"copy kernel: {copy_gbs:.0f} GB/s (read + write)")
 
+    NR = args.sources
+    B_all = torch.stack(B) if NR > 1 else None
+
     def one_step(record):
-        for k, b in enumerate(B):
-            for prec in ("mixed", "fp64"):
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                x, st = lat.solve(b, prec=prec, tol=args.tol)
-                torch.cuda.synchronize()
-                dt = time.perf_counter() - t0
-                record["solves"].append({"prec": prec, "source": k, "s": dt, **st})
-                record["x"][(prec, k)] = x
-            rel = float(torch.linalg.norm(record["x"][("mixed", k)] - record["x"][("fp64", k)])
-                        / torch.linalg.norm(record["x"][("fp64", k)]))
-            record["mixed_vs_fp64"].append(rel)
-            record["x"].clear()
+        # the headline: all sources in one multi-source solve per precision
+        xs = {}
+        for prec in ("mixed", "fp64"):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if NR > 1:
+                x, sts = lat.solve_multi(B_all, prec=prec, tol=args.tol)
+            else:
+                x1, st1 = lat.solve(B[0], prec=prec, tol=args.tol)
+                x, sts = x1.unsqueeze(0), [st1]
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            record["multi"].append({"prec": prec, "s": dt, "per_source_s": dt / NR, "iters": sts[0]["iters"],
+                                    "reliable_updates": sts[0]["reliable_updates"],
+                                    "true_rel_res_max": max(st["true_rel_res"] for st in sts),
+                                    "converged_all": all(st["converged"] == 1 for st in sts),
+                                    "flops": sum(st["flops"] for st in sts)})
+            xs[prec] = x
+        for k in range(NR):
+            record["mixed_vs_fp64"].append(float(torch.linalg.norm(xs["mixed"][k] - xs["fp64"][k])
+                                                 / torch.linalg.norm(xs["fp64"][k])))
+        del xs
+        # one source on its own, for comparison
+        for prec in ("mixed", "fp64"):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            x, st = lat.solve(B[0], prec=prec, tol=args.tol)
+            torch.cuda.synchronize()
+            record["single"].append({"prec": prec, "s": time.perf_counter() - t0, **st})
+            del x
         if not args.no_force:
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -309,9 +367,12 @@ def main() -> int:
         lat.apply("MdagM", XI, prec="mixed")
         for prec in ("mixed", "fp64"):
             record["stencil"][prec].append(lat.time_stencil(prec, args.stencil_reps))
+            if NR > 1:
+                record["stencil_multi"][prec].append(lat.time_stencil_multi(NR, prec, args.stencil_reps))
 
     def new_record():
-        return {"solves": [], "x": {}, "mixed_vs_fp64": [], "force": [], "stencil": {"mixed": [], "fp64": []}}
+        return {"multi": [], "single": [], "mixed_vs_fp64": [], "force": [],
+                "stencil": {"mixed": [], "fp64": []}, "stencil_multi": {"mixed": [], "fp64": []}}
 
     for w in range(args.warmup):
         log(f"warmup step {w + 1}/{args.warmup}")
@@ -325,35 +386,40 @@ def main() -> int:
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t_start
 
-    def agg(prec, key):
-        return [r[key] for r in rec["solves"] if r["prec"] == prec]
+    def multi_of(prec, key):
+        return [r[key] for r in rec["multi"] if r["prec"] == prec]
 
-    tts = {p: float(np.mean(agg(p, "s"))) for p in ("mixed", "fp64")}
-    st_ms = {p: np.mean(np.array(rec["stencil"][p]), axis=0) for p in ("mixed", "fp64")}
-    mdagm = {}
-    for p in ("mixed", "fp64"):
-        k1_ms, k2_ms, app_ms = (float(v) for v in st_ms[p])
-        mc = args.mixed_clover
-        gbs = mdagm_bytes_per_site(p, mc) * Vh / (app_ms * 1e-3) / 1e9
-        mdagm[p] = {
-            "ms": app_ms,
-            "GB_s": gbs,
-            "pct_hbm_peak": 100.0 * gbs / HBM_PEAK_GBS,
-            "pct_copy_bw": 100.0 * gbs / copy_gbs,
-            "GFLOP_s": 2 * FLOPS_PER_SITE * V / (app_ms * 1e-3) / 1e9,
-            "k1_ms": k1_ms,
-            "k2_ms": k2_ms,
-            "k1_GB_s": k1_bytes_per_site(p, mixed_clover=mc) * Vh / (k1_ms * 1e-3) / 1e9,
-            "k2_GB_s": k2_bytes_per_site(p, mixed_clover=mc) * Vh / (k2_ms * 1e-3) / 1e9,
-        }
-    k1_bytes = k1_bytes_per_site("mixed", mixed_clover=args.mixed_clover) * Vh
-    k1_ms = mdagm["mixed"]["k1_ms"]
-    achieved = k1_bytes / (k1_ms * 1e-3) / 1e9
-    traffic = traffic_for(Vh) if args.mixed_clover == 16 else None
+    def single_of(prec, key):
+        return [r[key] for r in rec["single"] if r["prec"] == prec]
+
+    tts = {p: float(np.mean(multi_of(p, "per_source_s"))) for p in ("mixed", "fp64")}
+    tts_single = {p: float(np.mean(single_of(p, "s"))) for p in ("mixed", "fp64")}
+    mc = args.mixed_clover
+
+    def stencil_summary(ms3, prec, nr):
+        k1_ms, k2_ms, app_ms = (float(v) for v in ms3)
+        gbs = mdagm_bytes_multi(prec, nr, mc) * Vh / (app_ms * 1e-3) / 1e9
+        return {"n_rhs": nr, "ms": app_ms, "ms_per_rhs": app_ms / nr, "GB_s": gbs,
+                "pct_hbm_peak": 100.0 * gbs / HBM_PEAK_GBS, "pct_copy_bw": 100.0 * gbs / copy_gbs,
+                "GFLOP_s": 2 * FLOPS_PER_SITE * V * nr / (app_ms * 1e-3) / 1e9,
+                "k1_ms": k1_ms, "k2_ms": k2_ms,
+                "k1_GB_s": k1_bytes_multi(prec, nr, mc) * Vh / (k1_ms * 1e-3) / 1e9,
+                "k2_GB_s": k2_bytes_multi(prec, nr, mc) * Vh / (k2_ms * 1e-3) / 1e9}
+
+    mdagm = {p: stencil_summary(np.mean(np.array(rec["stencil"][p]), axis=0), p, 1) for p in ("mixed", "fp64")}
+    mdagm_multi = ({p: stencil_summary(np.mean(np.array(rec["stencil_multi"][p]), axis=0), p, NR)
+                    for p in ("mixed", "fp64")} if NR > 1 else None)
+    # roofline: the mixed k1 launch of the timed (multi-source) solve
+    head = mdagm_multi["mixed"] if NR > 1 else mdagm["mixed"]
+    k1_bytes = k1_bytes_multi("mixed", NR, mc) * Vh
+    achieved = k1_bytes / (head["k1_ms"] * 1e-3) / 1e9
+    tkey = "k1_mixed_multi" if NR > 1 else "k1_mixed_single"
+    traffic = traffic_for(tkey, Vh) if (mc == 16 and (NR == 8 or NR == 1)) else None
+    kname = "dslash_kernel<float, 0, true, false, " + ("true" if NR > 1 else "false") + ", ...CloverH>"
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                "kernel": "dslash_kernel<float, 0, true, false, ...CloverH> (mixed k1: t_o = A_oo^-1 H_oe p_e, binary16 "
-                          f"spinors/links, {'FP32' if args.mixed_clover == 32 else 'binary16'} clover)",
+                "kernel": f"{kname} (mixed k1: t_o = A_oo^-1 H_oe p_e for {NR} interleaved sources, binary16 "
+                          f"spinors/links, {'FP32' if mc == 32 else 'binary16'} clover)",
                 "bytes_per_launch": k1_bytes}
 
     out = {
@@ -371,19 +437,25 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": f"{lx}x{ly}x{lz}x{lt} even-odd Wilson-clover CG to tol {args.tol:g}, "
                                f"kappa {kappa}, c_sw {csw}, SU(3) links exp(iH) width {width}, "
-                               f"{args.sources} Gaussian sources, mixed vs FP64 + force",
+                               f"{args.sources} Gaussian sources solved together (time per source), "
+                               f"mixed vs FP64 + force",
                    "dims": list(dims), "sources": args.sources, "tol": args.tol},
         "mixed_tts_s": tts["mixed"],
         "fp64_tts_s": tts["fp64"],
         "speedup_mixed_vs_fp64": tts["fp64"] / tts["mixed"],
-        "iters": {p: float(np.mean(agg(p, "iters"))) for p in ("mixed", "fp64")},
-        "reliable_updates_mixed": float(np.mean(agg("mixed", "reliable_updates"))),
-        "true_rel_res_max": {p: float(np.max(agg(p, "true_rel_res"))) for p in ("mixed", "fp64")},
-        "converged_all": all(r["converged"] == 1 for r in rec["solves"]),
+        "iters": {p: float(np.mean(multi_of(p, "iters"))) for p in ("mixed", "fp64")},
+        "reliable_updates_mixed": float(np.mean(multi_of("mixed", "reliable_updates"))),
+        "true_rel_res_max": {p: float(np.max(multi_of(p, "true_rel_res_max"))) for p in ("mixed", "fp64")},
+        "converged_all": all(r["converged_all"] for r in rec["multi"]),
         "mixed_vs_fp64_rel_diff_max": float(np.max(rec["mixed_vs_fp64"])),
-        "solver_GFLOP_s": {p: float(np.mean([r["flops"] / r["s"] for r in rec["solves"] if r["prec"] == p])) / 1e9
+        "solver_GFLOP_s": {p: float(np.mean([r["flops"] / r["s"] for r in rec["multi"] if r["prec"] == p])) / 1e9
                            for p in ("mixed", "fp64")},
+        "single_source": {p: {"tts_s": tts_single[p], "iters": float(np.mean(single_of(p, "iters"))),
+                              "true_rel_res": float(np.max(single_of(p, "true_rel_res")))}
+                          for p in ("mixed", "fp64")},
+        "multi_source_speedup": {p: tts_single[p] / tts[p] for p in ("mixed", "fp64")},
         "mdagm": mdagm,
+        "mdagm_multi": mdagm_multi,
         "copy_GB_s": copy_gbs,
         "force_s": float(np.mean([f["s"] for f in rec["force"]])) if rec["force"] else None,
         "roofline": roofline,
@@ -395,7 +467,7 @@ def main() -> int:
         out["trajectory"] = {f"{lx}x{ly}x{lz}x{lt}": trajectory_run(lat, dims, U, 2, 0.02, args.beta, "mixed",
                                                                      args.tol)}
     lat.close()
-    del B, U, XI, phi
+    del B, B_all, U, XI, phi
     torch.cuda.empty_cache()
     if not args.no_secondary:
         out["secondary"] = {
@@ -408,8 +480,7 @@ def main() -> int:
                                                                          0.02, args.beta, prec, args.tol)
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle Mhat^dag Mhat at the full workload")
-        fp64_iters = int(round(np.mean([r["iters"] for r in rec["solves"]
-                                        if r["prec"] == "fp64" and r["source"] == 0])))
+        fp64_iters = int(round(np.mean(single_of("fp64", "iters"))))
         out["cpu_baseline"] = cpu_baseline(dims, kappa, csw, u_np, b_np[0], fp64_iters)
     else:
         out["cpu_baseline"] = None

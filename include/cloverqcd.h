@@ -287,6 +287,13 @@ int qcd_encode_half(qcd_ctx *ctx, int n, const void *in_dev, void *codes_dev, fl
  * (timing does not depend on them). */
 int qcd_time_stencil(qcd_ctx *ctx, int prec, int n, double ms[3]);
 
+/* As qcd_time_stencil for n_rhs (1..QCD_MAX_RHS) right-hand sides
+ * interleaved as in qcd_solve_multi: each launch processes all of them (one
+ * work-item per site and right-hand side, links and clover read once per
+ * site).  Uses (and on first use allocates) the multi-source work vectors;
+ * their contents are whatever the last multi-source call left, zero before. */
+int qcd_time_stencil_multi(qcd_ctx *ctx, int prec, int n_rhs, int n, double ms[3]);
+
 /* Plain device copy of n_bytes (multiple of 16, 16-byte aligned pointers),
  * a bandwidth calibration kernel on the context's stream. */
 int qcd_stream_copy(qcd_ctx *ctx, void *dst_dev, const void *src_dev, uint64_t n_bytes);

@@ -83,6 +83,7 @@ SIGNATURES = {
                            ctypes.POINTER(_D), ctypes.POINTER(SolverStats)], _I),
     "qcd_encode_half": ([_P, _I, _P, _P, _P], _I),
     "qcd_time_stencil": ([_P, _I, _I, ctypes.POINTER(ctypes.c_double)], _I),
+    "qcd_time_stencil_multi": ([_P, _I, _I, _I, ctypes.POINTER(ctypes.c_double)], _I),
     "qcd_stream_copy": ([_P, _P, _P, ctypes.c_uint64], _I),
 }
 
@@ -284,6 +285,13 @@ def qcd_time_stencil(ctx, prec: int, n: int) -> tuple[float, float, float]:
     """(k1 ms per launch, k2 ms per launch, Mhat^dag Mhat ms per application)."""
     ms = (ctypes.c_double * 3)()
     check(lib().qcd_time_stencil(ctx, int(prec), int(n), ms))
+    return ms[0], ms[1], ms[2]
+
+
+def qcd_time_stencil_multi(ctx, prec: int, n_rhs: int, n: int) -> tuple[float, float, float]:
+    """As qcd_time_stencil, each launch covering n_rhs interleaved right-hand sides."""
+    ms = (ctypes.c_double * 3)()
+    check(lib().qcd_time_stencil_multi(ctx, int(prec), int(n_rhs), int(n), ms))
     return ms[0], ms[1], ms[2]
 
 

@@ -182,6 +182,13 @@ int alloc_work(const Geom& g, Work& w, int lg, bool all_slots) {
   if (rc == QCD_OK && hipHostGetDevicePointer((void**)&w.mbox_dev, w.mbox_host, 0) != hipSuccess)
     rc = fail(QCD_EHIP, "hipHostGetDevicePointer failed");
   if (rc == QCD_OK && hipMemset(w.st, 0, w.nr * sizeof(CgState)) != hipSuccess) rc = fail(QCD_EHIP, "hipMemset failed");
+  // defined contents for timing calls made before any solve
+  for (int k = 0; k < NSLOT && rc == QCD_OK; ++k)
+    if (w.vec[k] && hipMemset(w.vec[k], 0, 12 * S * sizeof(double2)) != hipSuccess) rc = fail(QCD_EHIP, "hipMemset failed");
+  for (int k = 0; k < NHSLOT && rc == QCD_OK; ++k)
+    if (w.hv[k] && (hipMemset(w.hv[k], 0, 3 * S * sizeof(uint4)) != hipSuccess ||
+                    hipMemset(w.hs[k], 0, S * sizeof(float)) != hipSuccess))
+      rc = fail(QCD_EHIP, "hipMemset failed");
   if (rc != QCD_OK) {
     free_work(w);
     return rc;
@@ -935,6 +942,23 @@ struct WorkGuard {
   ~WorkGuard() { c->w = &c->w1; }
 };
 
+// Make the multi-source work set hold 1 << lg right-hand sides.
+int use_multi(qcd_ctx* c, int lg) {
+  if (c->wm.st == nullptr || c->wm_lg_alloc < lg) {
+    free_work(c->wm);
+    c->wm_lg_alloc = -1;
+    QCHK(alloc_work(c->g, c->wm, lg, false));
+    c->wm_lg_alloc = lg;
+  }
+  Work& w = c->wm;
+  w.lg = lg;
+  w.nr = 1 << lg;
+  w.gv = c->g;
+  w.gv.Vh = c->g.Vh << lg;
+  w.gv.stride = c->g.stride << lg;
+  return QCD_OK;
+}
+
 // Solve M x = b for the work set's right-hand sides (n of them, packed by the
 // caller into V_B_E / V_B_O); writes x into V_X / V_OUT_O and the stats.
 int solve_packed(qcd_ctx* c, const qcd_solver_params* p, int n, qcd_solver_stats* stats,
@@ -1027,18 +1051,8 @@ int qcd_solve_multi(qcd_ctx* c, const qcd_solver_params* p, int n_rhs, const voi
   int lg = 0;
   while ((1 << lg) < n_rhs) ++lg;
   // a set allocated for more right-hand sides serves fewer (its buffers are larger)
-  if (c->wm.st == nullptr || c->wm_lg_alloc < lg) {
-    free_work(c->wm);
-    c->wm_lg_alloc = -1;
-    QCHK(alloc_work(c->g, c->wm, lg, false));
-    c->wm_lg_alloc = lg;
-  }
+  QCHK(use_multi(c, lg));
   Work& w = c->wm;
-  w.lg = lg;
-  w.nr = 1 << lg;
-  w.gv = c->g;
-  w.gv.Vh = c->g.Vh << lg;
-  w.gv.stride = c->g.stride << lg;
   // every state posts in step from zero
   HIPCHK(hipMemsetAsync(w.st, 0, ((size_t)1 << c->wm_lg_alloc) * sizeof(CgState), c->stream));
   w.post_ctr = 0;
@@ -1299,12 +1313,13 @@ int qcd_md_trajectory(qcd_ctx* c, const qcd_md_params* md, void* U_dev, double* 
   return QCD_OK;
 }
 
-int qcd_time_stencil(qcd_ctx* c, int prec, int n, double* ms) {
-  QCHK(check_ctx(c));
-  if (!ms) return fail(QCD_EINVAL, "null output pointer");
-  if (n < 1 || n > 4096) return fail(QCD_EINVAL, "n must lie in [1, 4096]");
-  if (prec != QCD_FP64 && prec != QCD_MIXED) return fail(QCD_EINVAL, "unknown precision");
-  QCHK(need_clover(c));
+}  // extern "C"
+
+namespace {
+
+// Events around each launch of n Mhat^dag Mhat applications on the active
+// work set; the vectors are slots a (input) -> b (hop) -> d -> e of the set.
+int time_stencil_impl(qcd_ctx* c, int prec, int n, double* ms, const int f[4], const int h[4]) {
   // n applications of Mhat^dag Mhat; an event before and after every launch
   constexpr int kEv = 5;
   hipEvent_t ev[kEv];
@@ -1320,21 +1335,21 @@ int qcd_time_stencil(qcd_ctx* c, int prec, int n, double* ms) {
     auto rec = [&](int k) { return hipEventRecord(ev[k], c->stream) == hipSuccess ? QCD_OK : fail(QCD_EHIP, "hipEventRecord failed"); };
     if (rc == QCD_OK) rc = rec(0);
     if (prec == QCD_FP64) {
-      if (rc == QCD_OK) rc = k1_f64(c, V_IN_E, V_T, false, nullptr);
+      if (rc == QCD_OK) rc = k1_f64(c, f[0], f[1], false, nullptr);
       if (rc == QCD_OK) rc = rec(1);
-      if (rc == QCD_OK) rc = k2_f64(c, V_IN_E, V_T, V_OUT_E, false, 0, 0, 0.0, false, nullptr);
+      if (rc == QCD_OK) rc = k2_f64(c, f[0], f[1], f[2], false, 0, 0, 0.0, false, nullptr);
       if (rc == QCD_OK) rc = rec(2);
-      if (rc == QCD_OK) rc = k1_f64(c, V_OUT_E, V_T, true, nullptr);
+      if (rc == QCD_OK) rc = k1_f64(c, f[2], f[1], true, nullptr);
       if (rc == QCD_OK) rc = rec(3);
-      if (rc == QCD_OK) rc = k2_f64(c, V_OUT_E, V_T, V_AUX, true, 0, 0, 0.0, false, nullptr);
+      if (rc == QCD_OK) rc = k2_f64(c, f[2], f[1], f[3], true, 0, 0, 0.0, false, nullptr);
     } else {
-      if (rc == QCD_OK) rc = k1_h(c, H_IN, H_T, false, nullptr);
+      if (rc == QCD_OK) rc = k1_h(c, h[0], h[1], false, nullptr);
       if (rc == QCD_OK) rc = rec(1);
-      if (rc == QCD_OK) rc = k2_h(c, H_IN, H_T, H_OUT, false, 0, 0, false, nullptr);
+      if (rc == QCD_OK) rc = k2_h(c, h[0], h[1], h[2], false, 0, 0, false, nullptr);
       if (rc == QCD_OK) rc = rec(2);
-      if (rc == QCD_OK) rc = k1_h(c, H_OUT, H_T, true, nullptr);
+      if (rc == QCD_OK) rc = k1_h(c, h[2], h[1], true, nullptr);
       if (rc == QCD_OK) rc = rec(3);
-      if (rc == QCD_OK) rc = k2_h(c, H_OUT, H_T, H_Q, true, 0, 0, false, nullptr);
+      if (rc == QCD_OK) rc = k2_h(c, h[2], h[1], h[3], true, 0, 0, false, nullptr);
     }
     if (rc == QCD_OK) rc = rec(4);
     if (rc == QCD_OK && hipEventSynchronize(ev[4]) != hipSuccess) rc = fail(QCD_EHIP, "hipEventSynchronize failed");
@@ -1351,6 +1366,37 @@ int qcd_time_stencil(qcd_ctx* c, int prec, int n, double* ms) {
   ms[1] = t_k2 / n;
   ms[2] = t_app / n;
   return QCD_OK;
+}
+
+int check_time_args(qcd_ctx* c, int prec, int n, double* ms) {
+  QCHK(check_ctx(c));
+  if (!ms) return fail(QCD_EINVAL, "null output pointer");
+  if (n < 1 || n > 4096) return fail(QCD_EINVAL, "n must lie in [1, 4096]");
+  if (prec != QCD_FP64 && prec != QCD_MIXED) return fail(QCD_EINVAL, "unknown precision");
+  QCHK(need_clover(c));
+  return QCD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int qcd_time_stencil(qcd_ctx* c, int prec, int n, double* ms) {
+  QCHK(check_time_args(c, prec, n, ms));
+  WorkGuard wg(c, &c->w1);
+  const int f[4] = {V_IN_E, V_T, V_OUT_E, V_AUX}, h[4] = {H_IN, H_T, H_OUT, H_Q};
+  return time_stencil_impl(c, prec, n, ms, f, h);
+}
+
+int qcd_time_stencil_multi(qcd_ctx* c, int prec, int n_rhs, int n, double* ms) {
+  QCHK(check_time_args(c, prec, n, ms));
+  if (n_rhs < 1 || n_rhs > QCD_MAX_RHS) return fail(QCD_EINVAL, "n_rhs must lie in [1, 16]");
+  int lg = 0;
+  while ((1 << lg) < n_rhs) ++lg;
+  QCHK(use_multi(c, lg));
+  WorkGuard wg(c, &c->wm);
+  const int f[4] = {V_P, V_T, V_Q, V_AUX}, h[4] = {H_P, H_T, H_Q, H_R};
+  return time_stencil_impl(c, prec, n, ms, f, h);
 }
 
 int qcd_encode_half(qcd_ctx* c, int n, const void* in_dev, void* codes_dev, float* scale_dev) {

@@ -49,7 +49,7 @@ struct DArgs {
 // branch the FP64 kernel runs out of registers and spills.
 // i: checkerboard site (links, clover); r: right-hand side (MULTI: spinor
 // element (cb << lg) | r, otherwise cb).
-template <int MU, bool G5IN, bool MULTI, typename R, class A>
+template <int MU, bool G5IN, bool MULTI, bool FUSED, typename R, class A>
 __device__ __forceinline__ void hop_dir(const A& a, int i, int r, const int x[4], Spinor<R>& acc) {
   using SIn = decltype(a.in);
   constexpr bool scaled = SpinorScale<SIn>::scaled;
@@ -87,7 +87,7 @@ __device__ __forceinline__ void hop_dir(const A& a, int i, int r, const int x[4]
 #pragma unroll
       for (int c = 0; c < 3; ++c) h.h[k][c] = sf * h.h[k][c];
   }
-  mul_mat(uf, h, uh);
+  mul_mat<FUSED>(uf, h, uh);
   accumulate<MU, -1>(acc, uh);
   project<MU, +1>(pb, h);
   if constexpr (scaled || MU == 3) {
@@ -96,7 +96,7 @@ __device__ __forceinline__ void hop_dir(const A& a, int i, int r, const int x[4]
 #pragma unroll
       for (int c = 0; c < 3; ++c) h.h[k][c] = sb * h.h[k][c];
   }
-  mul_adj(ub, h, uh);
+  mul_adj<FUSED>(ub, h, uh);
   accumulate<MU, +1>(acc, uh);
 }
 
@@ -117,10 +117,13 @@ __global__ void __launch_bounds__(256) dslash_kernel(A a) {
     cb_coords(i, a.par_out, a.g, x);
     Spinor<R> acc;
     zero(acc);
-    hop_dir<0, G5IN, MULTI>(a, i, r, x, acc);
-    hop_dir<1, G5IN, MULTI>(a, i, r, x, acc);
-    hop_dir<2, G5IN, MULTI>(a, i, r, x, acc);
-    hop_dir<3, G5IN, MULTI>(a, i, r, x, acc);
+    // fused matvecs except in the FP32 site-term kernel (k2), which would
+    // then need twice the registers (half the wavefronts per SIMD)
+    constexpr bool FUSED = SITE == 0 || sizeof(R) == 8;
+    hop_dir<0, G5IN, MULTI, FUSED>(a, i, r, x, acc);
+    hop_dir<1, G5IN, MULTI, FUSED>(a, i, r, x, acc);
+    hop_dir<2, G5IN, MULTI, FUSED>(a, i, r, x, acc);
+    hop_dir<3, G5IN, MULTI, FUSED>(a, i, r, x, acc);
     // hop scale, with gamma5 on the output folded into the lower spins
     const R c = R(a.c), cl = a.g5out ? R(-a.c) : R(a.c);
 #pragma unroll

@@ -44,6 +44,36 @@ __device__ __forceinline__ Cx<R> tmi(Cx<R> a) { return {a.im, -a.re}; }  // -i a
 template <typename R>
 __device__ __forceinline__ R norm2(Cx<R> a) { return a.re * a.re + a.im * a.im; }
 
+// Complex multiply-accumulate as four fused multiply-adds, so that the
+// product is never rounded on its own and the sum needs no separate add:
+// cfma = acc + a b, cfmac = acc + conj(a) b, cfms = acc - a b.
+__device__ __forceinline__ float fmar(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmar(double a, double b, double c) { return __builtin_fma(a, b, c); }
+template <typename R>
+__device__ __forceinline__ Cx<R> cfma(Cx<R> a, Cx<R> b, Cx<R> acc) {
+  acc.re = fmar(a.re, b.re, acc.re);
+  acc.re = fmar(-a.im, b.im, acc.re);
+  acc.im = fmar(a.re, b.im, acc.im);
+  acc.im = fmar(a.im, b.re, acc.im);
+  return acc;
+}
+template <typename R>
+__device__ __forceinline__ Cx<R> cfmac(Cx<R> a, Cx<R> b, Cx<R> acc) {
+  acc.re = fmar(a.re, b.re, acc.re);
+  acc.re = fmar(a.im, b.im, acc.re);
+  acc.im = fmar(a.re, b.im, acc.im);
+  acc.im = fmar(-a.im, b.re, acc.im);
+  return acc;
+}
+template <typename R>
+__device__ __forceinline__ Cx<R> cfms(Cx<R> a, Cx<R> b, Cx<R> acc) {
+  acc.re = fmar(-a.re, b.re, acc.re);
+  acc.re = fmar(a.im, b.im, acc.re);
+  acc.im = fmar(-a.re, b.im, acc.im);
+  acc.im = fmar(-a.im, b.re, acc.im);
+  return acc;
+}
+
 // ------------------------------------------------------------------ register types
 template <typename R>
 struct Spinor {
@@ -82,23 +112,34 @@ __device__ __forceinline__ double site_norm2(const Spinor<R>& s) {
   return n;
 }
 
-// U h, colour matrix times the two colour vectors of a half spinor
-template <typename R>
+// U h, colour matrix times the two colour vectors of a half spinor.  FUSED:
+// each row as one chain of fused multiply-adds (fewer instructions); the
+// unfused form (products, then sums) schedules into fewer registers where a
+// kernel is short of them.
+template <bool FUSED = true, typename R>
 __device__ __forceinline__ void mul_mat(const Mat<R>& u, const Half<R>& in, Half<R>& out) {
 #pragma unroll
   for (int k = 0; k < 2; ++k)
 #pragma unroll
-    for (int a = 0; a < 3; ++a)
-      out.h[k][a] = u.m[a][0] * in.h[k][0] + u.m[a][1] * in.h[k][1] + u.m[a][2] * in.h[k][2];
+    for (int a = 0; a < 3; ++a) {
+      if constexpr (FUSED)
+        out.h[k][a] = cfma(u.m[a][2], in.h[k][2], cfma(u.m[a][1], in.h[k][1], u.m[a][0] * in.h[k][0]));
+      else
+        out.h[k][a] = u.m[a][0] * in.h[k][0] + u.m[a][1] * in.h[k][1] + u.m[a][2] * in.h[k][2];
+    }
 }
 // U^dag h
-template <typename R>
+template <bool FUSED = true, typename R>
 __device__ __forceinline__ void mul_adj(const Mat<R>& u, const Half<R>& in, Half<R>& out) {
 #pragma unroll
   for (int k = 0; k < 2; ++k)
 #pragma unroll
-    for (int a = 0; a < 3; ++a)
-      out.h[k][a] = cmulc(u.m[0][a], in.h[k][0]) + cmulc(u.m[1][a], in.h[k][1]) + cmulc(u.m[2][a], in.h[k][2]);
+    for (int a = 0; a < 3; ++a) {
+      if constexpr (FUSED)
+        out.h[k][a] = cfmac(u.m[2][a], in.h[k][2], cfmac(u.m[1][a], in.h[k][1], cmulc(u.m[0][a], in.h[k][0])));
+      else
+        out.h[k][a] = cmulc(u.m[0][a], in.h[k][0]) + cmulc(u.m[1][a], in.h[k][1]) + cmulc(u.m[2][a], in.h[k][2]);
+    }
 }
 
 template <typename R>
@@ -107,7 +148,7 @@ __device__ __forceinline__ Mat<R> mm(const Mat<R>& a, const Mat<R>& b) {
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
-    for (int j = 0; j < 3; ++j) c.m[i][j] = a.m[i][0] * b.m[0][j] + a.m[i][1] * b.m[1][j] + a.m[i][2] * b.m[2][j];
+    for (int j = 0; j < 3; ++j) c.m[i][j] = cfma(a.m[i][2], b.m[2][j], cfma(a.m[i][1], b.m[1][j], a.m[i][0] * b.m[0][j]));
   return c;
 }
 template <typename R>
@@ -418,7 +459,7 @@ __device__ __forceinline__ void reconstruct_row2(Mat<R>& u) {
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
     const int j1 = (j + 1) % 3, j2 = (j + 2) % 3;
-    u.m[2][j] = conj(u.m[0][j1] * u.m[1][j2] - u.m[0][j2] * u.m[1][j1]);
+    u.m[2][j] = conj(cfms(u.m[0][j2], u.m[1][j1], u.m[0][j1] * u.m[1][j2]));
   }
 }
 template <typename R, int NC>

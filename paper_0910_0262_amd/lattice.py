@@ -174,6 +174,10 @@ class Lattice:
         """(k1 ms/launch, k2 ms/launch, Mhat^dag Mhat ms/application) on the current fields."""
         return capi.qcd_time_stencil(self._ctx, _PREC[prec], n)
 
+    def time_stencil_multi(self, n_rhs, prec="mixed", n=20):
+        """(k1, k2, Mhat^dag Mhat) ms per launch / application for n_rhs interleaved right-hand sides."""
+        return capi.qcd_time_stencil_multi(self._ctx, _PREC[prec], n_rhs, n)
+
     def stream_copy(self, dst: torch.Tensor, src: torch.Tensor):
         capi.qcd_stream_copy(self._ctx, dst, src)
 
