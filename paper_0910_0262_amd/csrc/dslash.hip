@@ -39,7 +39,31 @@ struct DArgs {
   const CgState* st;
   double* partial;
   int lg;  // log2 of the number of interleaved right-hand sides (MULTI kernels)
+  // MULTI site order: z-tiles of 1 << tile_lg planes, t inside a tile
+  int tile_lg, plane;  // plane = (Lx / 2) Ly checkerboard sites per z-t plane
+  double inv_plane, inv_t;
 };
+
+// Site of the multi-source kernel's j-th work position.  The sites are taken
+// in xy-planes, then z within a tile of 1 << tile_lg planes, then t, then
+// the next z-tile: neighbours in t are two tiles' worth of sites apart in
+// this order (in x-fastest order they would be two whole t-slices apart,
+// which with 8 interleaved sources no longer fits the L2 of an XCD).
+template <class A>
+__device__ __forceinline__ int multi_site(const A& a, int j, int x[4]) {
+  const Geom& g = a.g;
+  int p, t, xh;
+  const int q = fdivmod(j, a.plane, a.inv_plane, p);
+  const int zi = q & ((1 << a.tile_lg) - 1);
+  const int zt = fdivmod(q >> a.tile_lg, g.X[3], a.inv_t, t);
+  const int z = (zt << a.tile_lg) + zi;
+  const int y = fdivmod(p, g.Xh, g.inv_xh, xh);
+  x[1] = y;
+  x[2] = z;
+  x[3] = t;
+  x[0] = 2 * xh + ((y + z + t + a.par_out) & 1);
+  return p + a.plane * (z + g.X[2] * t);
+}
 
 // One direction mu: the forward hop (1 - gamma_mu) U_mu(x) psi(x + mu) and
 // the backward hop (1 + gamma_mu) U_mu(x - mu)^dag psi(x - mu).  gamma5 on
@@ -108,13 +132,19 @@ template <typename R, int SITE, bool POST, bool G5IN, bool MULTI, class A>
 __global__ void __launch_bounds__(256) dslash_kernel(A a) {
   if (!MULTI && a.st != nullptr && a.st->halt) return;  // uniform over the grid
   const int blk = xcd_block(blockIdx.x, gridDim.x);
-  const int e = blk * blockDim.x + threadIdx.x;  // spinor element
-  const int i = MULTI ? (e >> a.lg) : e;         // checkerboard site
-  const int r = MULTI ? (e & ((1 << a.lg) - 1)) : 0;
+  const int w = blk * blockDim.x + threadIdx.x;  // work position
+  const int r = MULTI ? (w & ((1 << a.lg) - 1)) : 0;
   double nrm = 0.0;
-  if (i < a.g.Vh) {
+  if ((MULTI ? (w >> a.lg) : w) < a.g.Vh) {
     int x[4];
-    cb_coords(i, a.par_out, a.g, x);
+    int i;  // checkerboard site
+    if constexpr (MULTI) {
+      i = multi_site(a, w >> a.lg, x);
+    } else {
+      i = w;
+      cb_coords(i, a.par_out, a.g, x);
+    }
+    const int e = MULTI ? ((i << a.lg) | r) : i;  // spinor element
     Spinor<R> acc;
     zero(acc);
     // fused matvecs except in the FP32 site-term kernel (k2), which would
@@ -225,6 +255,11 @@ static hipError_t run_g5(const Geom& g, const DslashOp& op, int block, hipStream
   a.st = op.st;
   a.partial = op.partial;
   a.lg = op.lg;
+  a.tile_lg = 0;
+  while (a.tile_lg < 2 && g.X[2] % (2 << a.tile_lg) == 0) ++a.tile_lg;
+  a.plane = g.Xh * g.X[1];
+  a.inv_plane = 1.0 / a.plane;
+  a.inv_t = 1.0 / g.X[3];
   const int nb = blocks_for(g.Vh << op.lg, block);
   if (op.lg > 0)
     hipLaunchKernelGGL((dslash_kernel<R, SITE, POST, G5IN, true, decltype(a)>), dim3(nb), dim3(block), 0, s, a);
