@@ -211,8 +211,24 @@ def secondary(name, dims, width, kappa, csw, tol, reps, n_apps):
         out[prec] = {"tts_s": float(np.median(ts)), "iters": int(np.median(its)), "mdagm_ms": app,
                      "mdagm_GB_s": gbs, "mdagm_GFLOP_s": 2 * FLOPS_PER_SITE * 2 * vh / (app * 1e-3) / 1e9,
                      "us_per_iter": 1e6 * float(np.median(ts)) / max(1, int(np.median(its)))}
+    # the same lattice with 8 sources solved together (latency shared by all of them)
+    bm = torch.stack([torch.as_tensor(synth.gaussian_source(dims, 0, k)).cuda() for k in range(8)])
+    for prec in ("mixed", "fp64"):
+        lat.solve_multi(bm, prec=prec, tol=tol)
+        ts = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, sts = lat.solve_multi(bm, prec=prec, tol=tol)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        out[prec]["multi8_tts_per_source_s"] = float(np.median(ts)) / 8
+        out[prec]["multi8_iters"] = sts[0]["iters"]
+    del bm
     lat.close()
-    log(f"secondary {name}: mixed {out['mixed']['tts_s'] * 1e3:.1f} ms, fp64 {out['fp64']['tts_s'] * 1e3:.1f} ms")
+    log(f"secondary {name}: mixed {out['mixed']['tts_s'] * 1e3:.2f} ms, fp64 {out['fp64']['tts_s'] * 1e3:.2f} ms; "
+        f"8 sources together: {out['mixed']['multi8_tts_per_source_s'] * 1e3:.2f} / "
+        f"{out['fp64']['multi8_tts_per_source_s'] * 1e3:.2f} ms per source")
     return out
 
 
