@@ -130,3 +130,58 @@ def test_hmd_step_mixed_solve():
     assert max_rel(U, ref["U"]) < 1e-9
     assert max_rel(P, ref["P"]) < 1e-9
     lat.close()
+
+
+@pytest.fixture(scope="module")
+def force16():
+    """The force lattice of the benchmark configurations: 16^4, kappa 0.125, c_sw 1, width 0.3."""
+    dims, kappa, csw = (16, 16, 16, 16), 0.125, 1.0
+    print("[force 16^4: oracle reference]", flush=True)
+    lat, setup, u, ud = make_case(dims, 0.3, kappa, csw, 2)
+    phi = setup.Mhat_dag(torch.as_tensor(synth.heatbath_xi(dims, 2)))
+    S, G, X, _ = O.action_and_gradient(torch.as_tensor(u), kappa, csw, phi, tol=1e-13)
+    F = O.project_force(torch.as_tensor(u), G)
+    yield lat, phi, (S, G, F, X)
+    lat.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_force_parity_16x4(force16, prec):
+    lat, phi, (S, G, F, X) = force16
+    S_g, G_g, F_g, X_g, st = lat.action_force(to_dev(phi), prec=prec, tol=1e-12)
+    print(f"  16^4 {prec}: iters={st['iters']}", flush=True)
+    assert abs(S_g - S) < 1e-10 * abs(S)
+    assert rel_err(X_g, X) < 1e-10
+    assert max_rel(G_g, G) < 1e-9
+    assert max_rel(F_g, F) < 1e-9
+
+
+def test_force_directional_fd_full_lattice():
+    """32^3 x 64 (the benchmark's lattice, force with the mixed solve inside):
+    the derivative of the action along exp(i eps sum_a Q^a T^a) U for a random
+    Q on every link equals sum F.Q (central difference, eps = 1e-4, of the
+    variational action 2 Re phi^dag X - |Mhat X|^2, solves at tol 1e-12)."""
+    dims, kappa, csw, eps = (32, 32, 32, 64), 0.1255, 1.0, 1e-4
+    print("[force 32^3x64: directional finite difference]", flush=True)
+    lat = Lattice(dims, kappa, csw)
+    U0 = to_dev(synth.random_su3_field(dims, 0.2, 0))
+    lat.load_gauge(U0)
+    phi = lat.apply("Mhatdag", to_dev(synth.heatbath_xi(dims, 0)))
+    _, _, F, _, _ = lat.action_force(phi, prec="mixed", tol=1e-12, want_X=False)
+    Q = to_dev(synth.momenta(dims, 5))
+    analytic = float((F * Q).sum())
+    vals = []
+    for sgn in (1.0, -1.0):
+        U = U0.clone()
+        # U <- exp(i sgn eps Q) U: a one-step trajectory with no action moves the
+        # links by two half steps of the same Q
+        lat.md_trajectory(U, Q.clone(), None, sgn * eps, 1, beta=0.0, n_f=0.0)
+        lat.load_gauge(U)
+        _, _, _, X, _ = lat.action_force(phi, prec="fp64", tol=1e-12, want_F=False)
+        y = lat.apply("Mhat", X)
+        vals.append(float(2.0 * torch.vdot(phi.reshape(-1), X.reshape(-1)).real
+                          - torch.vdot(y.reshape(-1), y.reshape(-1)).real))
+    fd = (vals[0] - vals[1]) / (2 * eps)
+    print(f"  fd={fd:.6e} analytic={analytic:.6e}", flush=True)
+    assert abs(fd - analytic) < 1e-3 * abs(analytic)
+    lat.close()
