@@ -185,6 +185,32 @@ def cpu_baseline(dims, kappa, csw, u_np, b_np, fp64_iters: int):
     }
 
 
+def oracle_check_16(tol_gpu=1e-12):
+    """Part of the CPU-baseline leg: the oracle's full solve of the 16^4 workload
+    (kappa 0.125, c_sw 1, width 0.3, source 0; tol 1e-13), timed on the host, and
+    the relative solution error of the GPU's FP64 and mixed solves against it."""
+    import oracle as O
+    from paper_0910_0262_amd import Lattice, synth
+
+    dims, kappa, csw = (16, 16, 16, 16), 0.125, 1.0
+    u = synth.random_su3_field(dims, 0.3, 0)
+    b = synth.gaussian_source(dims, 0, 0)
+    t0 = time.perf_counter()
+    ref = O.solve_full(O.CloverSetup(torch.as_tensor(u), kappa, csw), torch.as_tensor(b), 1e-13)
+    t_oracle = time.perf_counter() - t0
+    lat = Lattice(dims, kappa, csw)
+    lat.load_gauge(torch.as_tensor(u).cuda())
+    out = {"dims": list(dims), "oracle_solve_s": t_oracle, "oracle_iters": ref.iters,
+           "cores": torch.get_num_threads(), "gpu_tol": tol_gpu}
+    for prec in ("fp64", "mixed"):
+        x, st = lat.solve(torch.as_tensor(b).cuda(), prec=prec, tol=tol_gpu)
+        out[f"{prec}_rel_solution_error"] = float(torch.linalg.norm(x.cpu() - ref.x) / torch.linalg.norm(ref.x))
+    lat.close()
+    log(f"oracle 16^4 solve {t_oracle:.1f} s; GPU relative solution error fp64 "
+        f"{out['fp64_rel_solution_error']:.1e}, mixed {out['mixed_rel_solution_error']:.1e}")
+    return out
+
+
 def secondary(name, dims, width, kappa, csw, tol, reps, n_apps):
     """Smaller lattices of the paper (abstract: 8x8x16x16 and 16^4): solve times
     and n_apps standalone Mhat^dag Mhat applications; not part of `value`."""
@@ -523,8 +549,10 @@ def main() -> int:
         log("cpu baseline: oracle Mhat^dag Mhat at the full workload")
         fp64_iters = int(round(np.mean(single_of("fp64", "iters"))))
         out["cpu_baseline"] = cpu_baseline(dims, kappa, csw, u_np, b_np[0], fp64_iters)
+        out["oracle_16x4"] = oracle_check_16()
     else:
         out["cpu_baseline"] = None
+        out["oracle_16x4"] = None
     print(json.dumps(out), flush=True)
     return 0
 
