@@ -65,11 +65,20 @@ __device__ __forceinline__ int multi_site(const A& a, int j, int x[4]) {
   return p + a.plane * (z + g.X[2] * t);
 }
 
+template <typename R>
+__device__ __forceinline__ void scale_half(Half<R>& h, R f) {
+#pragma unroll
+  for (int k = 0; k < 2; ++k)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) h.h[k][c] = f * h.h[k][c];
+}
+
 // One direction mu: the forward hop (1 - gamma_mu) U_mu(x) psi(x + mu) and
 // the backward hop (1 + gamma_mu) U_mu(x - mu)^dag psi(x - mu).  gamma5 on
 // the input (G5IN) is a compile-time sign that folds into the projection;
-// the antiperiodic-time sign and a binary16 field's per-site scale multiply
-// the projected half spinor once.  No branch may split this block: with a
+// a binary16 field's per-site scale (with the antiperiodic-time sign) enters
+// the multiply-adds that accumulate U h; an unscaled field takes the sign on
+// the projected half spinor.  No branch may split this block: with a
 // branch the FP64 kernel runs out of registers and spills.
 // i: checkerboard site (links, clover); r: right-hand side (MULTI: spinor
 // element (cb << lg) | r, otherwise cb).
@@ -105,23 +114,19 @@ __device__ __forceinline__ void hop_dir(const A& a, int i, int r, const int x[4]
   }
   Half<R> h, uh;
   project<MU, -1>(pf, h);
-  if constexpr (scaled || MU == 3) {
-#pragma unroll
-    for (int k = 0; k < 2; ++k)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) h.h[k][c] = sf * h.h[k][c];
-  }
+  if constexpr (!scaled && MU == 3) scale_half(h, sf);
   mul_mat<FUSED>(uf, h, uh);
-  accumulate<MU, -1>(acc, uh);
+  if constexpr (scaled)
+    accumulate<MU, -1>(acc, uh, sf);
+  else
+    accumulate<MU, -1>(acc, uh);
   project<MU, +1>(pb, h);
-  if constexpr (scaled || MU == 3) {
-#pragma unroll
-    for (int k = 0; k < 2; ++k)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) h.h[k][c] = sb * h.h[k][c];
-  }
+  if constexpr (!scaled && MU == 3) scale_half(h, sb);
   mul_adj<FUSED>(ub, h, uh);
-  accumulate<MU, +1>(acc, uh);
+  if constexpr (scaled)
+    accumulate<MU, +1>(acc, uh, sb);
+  else
+    accumulate<MU, +1>(acc, uh);
 }
 
 // MULTI: one work-item per (site, right-hand side) with the right-hand side
@@ -129,7 +134,8 @@ __device__ __forceinline__ void hop_dir(const A& a, int i, int r, const int x[4]
 // loads; halted right-hand sides keep computing with alpha = 0 (the grid
 // cannot return early for some of them).
 template <typename R, int SITE, bool POST, bool G5IN, bool MULTI, class A>
-__global__ void __launch_bounds__(256) dslash_kernel(A a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 1)))
+dslash_kernel(A a) {
   if (!MULTI && a.st != nullptr && a.st->halt) return;  // uniform over the grid
   const int blk = xcd_block(blockIdx.x, gridDim.x);
   const int w = blk * blockDim.x + threadIdx.x;  // work position
@@ -154,25 +160,35 @@ __global__ void __launch_bounds__(256) dslash_kernel(A a) {
     hop_dir<1, G5IN, MULTI, FUSED>(a, i, r, x, acc);
     hop_dir<2, G5IN, MULTI, FUSED>(a, i, r, x, acc);
     hop_dir<3, G5IN, MULTI, FUSED>(a, i, r, x, acc);
-    // hop scale, with gamma5 on the output folded into the lower spins
+    // hop scale, with gamma5 on the output folded into the lower spins; with
+    // no site term and a scaled post clover it joins the blocks' scales
     const R c = R(a.c), cl = a.g5out ? R(-a.c) : R(a.c);
+    constexpr bool HOP_IN_CLOVER = POST && SITE == 0 && CloverScale<decltype(a.cpost)>::scaled;
+    // the FP32 clover products as fused chains; FP64 (HBM-bound) keeps the
+    // form that needs fewer registers
+    constexpr bool FUSED_CL = FUSED && sizeof(R) == 4;
+    if constexpr (!HOP_IN_CLOVER) {
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      acc.v[0][k] = c * acc.v[0][k];
-      acc.v[1][k] = c * acc.v[1][k];
-      acc.v[2][k] = cl * acc.v[2][k];
-      acc.v[3][k] = cl * acc.v[3][k];
+      for (int k = 0; k < 3; ++k) {
+        acc.v[0][k] = c * acc.v[0][k];
+        acc.v[1][k] = c * acc.v[1][k];
+        acc.v[2][k] = cl * acc.v[2][k];
+        acc.v[3][k] = cl * acc.v[3][k];
+      }
     }
     if constexpr (SITE != 0) {
       Spinor<R> sv;
       load_once(a.site, e, sv);
-      if constexpr (SITE == 2) apply_clover(a.cpre, i, sv);
+      if constexpr (SITE == 2) apply_clover<FUSED_CL>(a.cpre, i, sv);
 #pragma unroll
       for (int s = 0; s < 4; ++s)
 #pragma unroll
         for (int k = 0; k < 3; ++k) acc.v[s][k] = acc.v[s][k] + sv.v[s][k];
     }
-    if constexpr (POST) apply_clover(a.cpost, i, acc);
+    if constexpr (HOP_IN_CLOVER)
+      apply_clover<FUSED_CL, true>(a.cpost, i, acc, c, cl);
+    else if constexpr (POST)
+      apply_clover<FUSED_CL>(a.cpost, i, acc);
     if (a.epi == 2) {
       Spinor<R> yv;
       load_once(a.y, e, yv);

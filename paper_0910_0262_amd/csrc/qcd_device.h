@@ -73,6 +73,31 @@ __device__ __forceinline__ Cx<R> cfms(Cx<R> a, Cx<R> b, Cx<R> acc) {
   acc.im = fmar(-a.im, b.re, acc.im);
   return acc;
 }
+// Leading product of a multiply-add chain.  In FP32 it is an FMA onto +0
+// (the product itself, up to the sign of a zero result), so that a binary16
+// operand is converted inside a mixed-precision FMA like the rest of the
+// chain instead of by an instruction of its own; FP64 keeps the product.
+template <typename R>
+__device__ __forceinline__ Cx<R> cmul0(Cx<R> a, Cx<R> b) {
+  if constexpr (sizeof(R) == 4)
+    return cfma(a, b, Cx<R>{R(0), R(0)});
+  else
+    return a * b;
+}
+template <typename R>
+__device__ __forceinline__ Cx<R> cmulc0(Cx<R> a, Cx<R> b) {
+  if constexpr (sizeof(R) == 4)
+    return cfmac(a, b, Cx<R>{R(0), R(0)});
+  else
+    return cmulc(a, b);
+}
+template <typename R>
+__device__ __forceinline__ Cx<R> rmul0(R s, Cx<R> a) {
+  if constexpr (sizeof(R) == 4)
+    return {fmar(s, a.re, R(0)), fmar(s, a.im, R(0))};
+  else
+    return s * a;
+}
 
 // ------------------------------------------------------------------ register types
 template <typename R>
@@ -123,7 +148,7 @@ __device__ __forceinline__ void mul_mat(const Mat<R>& u, const Half<R>& in, Half
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       if constexpr (FUSED)
-        out.h[k][a] = cfma(u.m[a][2], in.h[k][2], cfma(u.m[a][1], in.h[k][1], u.m[a][0] * in.h[k][0]));
+        out.h[k][a] = cfma(u.m[a][2], in.h[k][2], cfma(u.m[a][1], in.h[k][1], cmul0(u.m[a][0], in.h[k][0])));
       else
         out.h[k][a] = u.m[a][0] * in.h[k][0] + u.m[a][1] * in.h[k][1] + u.m[a][2] * in.h[k][2];
     }
@@ -136,7 +161,7 @@ __device__ __forceinline__ void mul_adj(const Mat<R>& u, const Half<R>& in, Half
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       if constexpr (FUSED)
-        out.h[k][a] = cfmac(u.m[2][a], in.h[k][2], cfmac(u.m[1][a], in.h[k][1], cmulc(u.m[0][a], in.h[k][0])));
+        out.h[k][a] = cfmac(u.m[2][a], in.h[k][2], cfmac(u.m[1][a], in.h[k][1], cmulc0(u.m[0][a], in.h[k][0])));
       else
         out.h[k][a] = cmulc(u.m[0][a], in.h[k][0]) + cmulc(u.m[1][a], in.h[k][1]) + cmulc(u.m[2][a], in.h[k][2]);
     }
@@ -459,7 +484,7 @@ __device__ __forceinline__ void reconstruct_row2(Mat<R>& u) {
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
     const int j1 = (j + 1) % 3, j2 = (j + 2) % 3;
-    u.m[2][j] = conj(cfms(u.m[0][j2], u.m[1][j1], u.m[0][j1] * u.m[1][j2]));
+    u.m[2][j] = conj(cfms(u.m[0][j2], u.m[1][j1], cmul0(u.m[0][j1], u.m[1][j2])));
   }
 }
 template <typename R, int NC>
@@ -577,17 +602,24 @@ struct CloverScale<CloverH> {
 };
 __device__ __forceinline__ float2 block_scales(const CloverH& c, int i) { return c.s[i]; }
 
-// v <- A v for one 6-vector (spins 2b, 2b+1)
-template <typename R>
+// v <- A v for one 6-vector (spins 2b, 2b+1).  FUSED: each row as one chain
+// of fused multiply-adds (with binary16 entries the conversion folds into
+// them too); the unfused form schedules into fewer registers.
+template <bool FUSED = false, typename R>
 __device__ __forceinline__ void block_mv(const Block<R>& a, Cx<R> v[6]) {
   Cx<R> out[6];
 #pragma unroll
   for (int r = 0; r < 6; ++r) {
-    Cx<R> s = a.d[r] * v[r];
+    Cx<R> s = FUSED ? rmul0(a.d[r], v[r]) : a.d[r] * v[r];
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
-      if (c > r) s = s + a.o[offd(r, c)] * v[c];
-      if (c < r) s = s + cmulc(a.o[offd(c, r)], v[c]);
+      if constexpr (FUSED) {
+        if (c > r) s = cfma(a.o[offd(r, c)], v[c], s);
+        if (c < r) s = cfmac(a.o[offd(c, r)], v[c], s);
+      } else {
+        if (c > r) s = s + a.o[offd(r, c)] * v[c];
+        if (c < r) s = s + cmulc(a.o[offd(c, r)], v[c]);
+      }
     }
     out[r] = s;
   }
@@ -595,8 +627,11 @@ __device__ __forceinline__ void block_mv(const Block<R>& a, Cx<R> v[6]) {
   for (int r = 0; r < 6; ++r) v[r] = out[r];
 }
 
-template <typename R, class CL>
-__device__ __forceinline__ void apply_clover(const CL& c, int i, Spinor<R>& s) {
+// s <- A s.  FACT: the two chiral halves of the result are multiplied by f0
+// (spins 0, 1) and f1 (spins 2, 3), which commutes with the block-diagonal A
+// and so costs nothing where the blocks carry a scale of their own.
+template <bool FUSED = false, bool FACT = false, typename R, class CL>
+__device__ __forceinline__ void apply_clover(const CL& c, int i, Spinor<R>& s, R f0 = R(1), R f1 = R(1)) {
   float2 sc = make_float2(1.f, 1.f);
   if constexpr (CloverScale<CL>::scaled) sc = block_scales(c, i);
 #pragma unroll
@@ -606,10 +641,12 @@ __device__ __forceinline__ void apply_clover(const CL& c, int i, Spinor<R>& s) {
     Cx<R> v[6];
 #pragma unroll
     for (int k = 0; k < 6; ++k) v[k] = s.v[2 * b + k / 3][k % 3];
-    block_mv(blk, v);
-    const R f = R(b == 0 ? sc.x : sc.y);
+    block_mv<FUSED>(blk, v);
+    R f = R(b == 0 ? sc.x : sc.y);
+    if constexpr (FACT) f = f * (b == 0 ? f0 : f1);
 #pragma unroll
-    for (int k = 0; k < 6; ++k) s.v[2 * b + k / 3][k % 3] = CloverScale<CL>::scaled ? f * v[k] : v[k];
+    for (int k = 0; k < 6; ++k)
+      s.v[2 * b + k / 3][k % 3] = (CloverScale<CL>::scaled || FACT) ? f * v[k] : v[k];
   }
 }
 
@@ -656,6 +693,40 @@ __device__ __forceinline__ void accumulate(Spinor<R>& a, const Half<R>& h) {
     } else {
       a.v[2][c] = a.v[2][c] + (S < 0 ? -h0 : h0);
       a.v[3][c] = a.v[3][c] + (S < 0 ? -h1 : h1);
+    }
+  }
+}
+// a += f * (the same reconstruction of h): the scale of the projected half
+// spinor (a binary16 field's site scale, the antiperiodic-time sign) rides on
+// the accumulating multiply-adds instead of costing 12 products of its own.
+template <typename R>
+__device__ __forceinline__ Cx<R> axpy(Cx<R> a, R f, Cx<R> h) {  // a + f h
+  return {fmar(f, h.re, a.re), fmar(f, h.im, a.im)};
+}
+template <typename R>
+__device__ __forceinline__ Cx<R> axpy_i(Cx<R> a, R f, Cx<R> h) {  // a + i f h
+  return {fmar(-f, h.im, a.re), fmar(f, h.re, a.im)};
+}
+template <int MU, int S, typename R>
+__device__ __forceinline__ void accumulate(Spinor<R>& a, const Half<R>& h, R f) {
+  const R g = S < 0 ? -f : f;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const Cx<R> h0 = h.h[0][c], h1 = h.h[1][c];
+    a.v[0][c] = axpy(a.v[0][c], f, h0);
+    a.v[1][c] = axpy(a.v[1][c], f, h1);
+    if (MU == 0) {  // S < 0: -i h1, -i h0
+      a.v[2][c] = axpy_i(a.v[2][c], g, h1);
+      a.v[3][c] = axpy_i(a.v[3][c], g, h0);
+    } else if (MU == 1) {  // S < 0: -h1, +h0
+      a.v[2][c] = axpy(a.v[2][c], g, h1);
+      a.v[3][c] = axpy(a.v[3][c], -g, h0);
+    } else if (MU == 2) {  // S < 0: -i h0, +i h1
+      a.v[2][c] = axpy_i(a.v[2][c], g, h0);
+      a.v[3][c] = axpy_i(a.v[3][c], -g, h1);
+    } else {  // S < 0: -h0, -h1
+      a.v[2][c] = axpy(a.v[2][c], g, h0);
+      a.v[3][c] = axpy(a.v[3][c], g, h1);
     }
   }
 }
