@@ -76,14 +76,15 @@ __device__ __forceinline__ void scale_half(Half<R>& h, R f) {
 // One direction mu: the forward hop (1 - gamma_mu) U_mu(x) psi(x + mu) and
 // the backward hop (1 + gamma_mu) U_mu(x - mu)^dag psi(x - mu).  gamma5 on
 // the input (G5IN) is a compile-time sign that folds into the projection;
-// a binary16 field's per-site scale (with the antiperiodic-time sign) enters
-// the multiply-adds that accumulate U h; an unscaled field takes the sign on
+// a binary16 field's per-site scale (with the antiperiodic-time sign and
+// the factors cu, cl of the upper and lower output spins) enters the
+// multiply-adds that accumulate U h; an unscaled field takes the sign on
 // the projected half spinor.  No branch may split this block: with a
 // branch the FP64 kernel runs out of registers and spills.
 // i: checkerboard site (links, clover); r: right-hand side (MULTI: spinor
 // element (cb << lg) | r, otherwise cb).
 template <int MU, bool G5IN, bool MULTI, bool FUSED, typename R, class A>
-__device__ __forceinline__ void hop_dir(const A& a, int i, int r, const int x[4], Spinor<R>& acc) {
+__device__ __forceinline__ void hop_dir(const A& a, int i, int r, const int x[4], Spinor<R>& acc, R cu, R cl) {
   using SIn = decltype(a.in);
   constexpr bool scaled = SpinorScale<SIn>::scaled;
   const Geom& g = a.g;
@@ -117,14 +118,14 @@ __device__ __forceinline__ void hop_dir(const A& a, int i, int r, const int x[4]
   if constexpr (!scaled && MU == 3) scale_half(h, sf);
   mul_mat<FUSED>(uf, h, uh);
   if constexpr (scaled)
-    accumulate<MU, -1>(acc, uh, sf);
+    accumulate<MU, -1>(acc, uh, sf * cu, sf * cl);
   else
     accumulate<MU, -1>(acc, uh);
   project<MU, +1>(pb, h);
   if constexpr (!scaled && MU == 3) scale_half(h, sb);
   mul_adj<FUSED>(ub, h, uh);
   if constexpr (scaled)
-    accumulate<MU, +1>(acc, uh, sb);
+    accumulate<MU, +1>(acc, uh, sb * cu, sb * cl);
   else
     accumulate<MU, +1>(acc, uh);
 }
@@ -151,23 +152,35 @@ dslash_kernel(A a) {
       cb_coords(i, a.par_out, a.g, x);
     }
     const int e = MULTI ? ((i << a.lg) | r) : i;  // spinor element
-    Spinor<R> acc;
-    zero(acc);
-    // fused matvecs except in the FP32 site-term kernel (k2), which would
-    // then need twice the registers (half the wavefronts per SIMD)
-    constexpr bool FUSED = SITE == 0 || sizeof(R) == 8;
-    hop_dir<0, G5IN, MULTI, FUSED>(a, i, r, x, acc);
-    hop_dir<1, G5IN, MULTI, FUSED>(a, i, r, x, acc);
-    hop_dir<2, G5IN, MULTI, FUSED>(a, i, r, x, acc);
-    hop_dir<3, G5IN, MULTI, FUSED>(a, i, r, x, acc);
-    // hop scale, with gamma5 on the output folded into the lower spins; with
-    // no site term and a scaled post clover it joins the blocks' scales
+    constexpr bool scaled = SpinorScale<decltype(a.in)>::scaled;
+    // hop scale, with gamma5 on the output folded into the lower spins
     const R c = R(a.c), cl = a.g5out ? R(-a.c) : R(a.c);
-    constexpr bool HOP_IN_CLOVER = POST && SITE == 0 && CloverScale<decltype(a.cpost)>::scaled;
+    // binary16 input: the site term comes first (its loads are consumed at
+    // once instead of living across the hops) and the hop scale rides on the
+    // accumulating multiply-adds; with no site term and a scaled post clover
+    // it joins the blocks' scales instead
+    constexpr bool SITE_FIRST = SITE != 0 && scaled;
+    constexpr bool HOP_IN_CLOVER = POST && SITE == 0 && scaled && CloverScale<decltype(a.cpost)>::scaled;
+    constexpr bool HOP_IN_ACC = SITE_FIRST;
+    // fused link matvecs except in the FP32 site-term kernel (k2), which
+    // would then spill at four wavefronts per SIMD
+    constexpr bool FUSED = SITE == 0 || sizeof(R) == 8;
     // the FP32 clover products as fused chains; FP64 (HBM-bound) keeps the
     // form that needs fewer registers
-    constexpr bool FUSED_CL = FUSED && sizeof(R) == 4;
-    if constexpr (!HOP_IN_CLOVER) {
+    constexpr bool FUSED_CL = (FUSED || SITE_FIRST) && sizeof(R) == 4;
+    Spinor<R> acc;
+    if constexpr (SITE_FIRST) {
+      load_once(a.site, e, acc);
+      if constexpr (SITE == 2) apply_clover<FUSED_CL>(a.cpre, i, acc);
+    } else {
+      zero(acc);
+    }
+    const R hu = HOP_IN_ACC ? c : R(1), hl = HOP_IN_ACC ? cl : R(1);
+    hop_dir<0, G5IN, MULTI, FUSED>(a, i, r, x, acc, hu, hl);
+    hop_dir<1, G5IN, MULTI, FUSED>(a, i, r, x, acc, hu, hl);
+    hop_dir<2, G5IN, MULTI, FUSED>(a, i, r, x, acc, hu, hl);
+    hop_dir<3, G5IN, MULTI, FUSED>(a, i, r, x, acc, hu, hl);
+    if constexpr (!HOP_IN_CLOVER && !HOP_IN_ACC) {
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
         acc.v[0][k] = c * acc.v[0][k];
@@ -176,7 +189,7 @@ dslash_kernel(A a) {
         acc.v[3][k] = cl * acc.v[3][k];
       }
     }
-    if constexpr (SITE != 0) {
+    if constexpr (SITE != 0 && !SITE_FIRST) {
       Spinor<R> sv;
       load_once(a.site, e, sv);
       if constexpr (SITE == 2) apply_clover<FUSED_CL>(a.cpre, i, sv);

@@ -707,14 +707,15 @@ template <typename R>
 __device__ __forceinline__ Cx<R> axpy_i(Cx<R> a, R f, Cx<R> h) {  // a + i f h
   return {fmar(-f, h.im, a.re), fmar(f, h.re, a.im)};
 }
+// fu multiplies the upper two spins of the reconstruction, fl the lower two.
 template <int MU, int S, typename R>
-__device__ __forceinline__ void accumulate(Spinor<R>& a, const Half<R>& h, R f) {
-  const R g = S < 0 ? -f : f;
+__device__ __forceinline__ void accumulate(Spinor<R>& a, const Half<R>& h, R fu, R fl) {
+  const R g = S < 0 ? -fl : fl;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     const Cx<R> h0 = h.h[0][c], h1 = h.h[1][c];
-    a.v[0][c] = axpy(a.v[0][c], f, h0);
-    a.v[1][c] = axpy(a.v[1][c], f, h1);
+    a.v[0][c] = axpy(a.v[0][c], fu, h0);
+    a.v[1][c] = axpy(a.v[1][c], fu, h1);
     if (MU == 0) {  // S < 0: -i h1, -i h0
       a.v[2][c] = axpy_i(a.v[2][c], g, h1);
       a.v[3][c] = axpy_i(a.v[3][c], g, h0);
