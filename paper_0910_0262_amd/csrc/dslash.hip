@@ -42,6 +42,7 @@ struct DArgs {
   // MULTI site order: z-tiles of 1 << tile_lg planes, t inside a tile
   int tile_lg, plane;  // plane = (Lx / 2) Ly checkerboard sites per z-t plane
   double inv_plane, inv_t;
+  float one;  // 1, opaque to the compiler (see project())
 };
 
 // Site of the multi-source kernel's j-th work position.  The sites are taken
@@ -114,14 +115,20 @@ __device__ __forceinline__ void hop_dir(const A& a, int i, int r, const int x[4]
     sb = (g.tb < 0 && x[3] == 0) ? -sb : sb;
   }
   Half<R> h, uh;
-  project<MU, -1>(pf, h);
+  if constexpr (scaled)
+    project<MU, -1>(pf, h, R(a.one));
+  else
+    project<MU, -1>(pf, h);
   if constexpr (!scaled && MU == 3) scale_half(h, sf);
   mul_mat<FUSED>(uf, h, uh);
   if constexpr (scaled)
     accumulate<MU, -1>(acc, uh, sf * cu, sf * cl);
   else
     accumulate<MU, -1>(acc, uh);
-  project<MU, +1>(pb, h);
+  if constexpr (scaled)
+    project<MU, +1>(pb, h, R(a.one));
+  else
+    project<MU, +1>(pb, h);
   if constexpr (!scaled && MU == 3) scale_half(h, sb);
   mul_adj<FUSED>(ub, h, uh);
   if constexpr (scaled)
@@ -289,6 +296,7 @@ static hipError_t run_g5(const Geom& g, const DslashOp& op, int block, hipStream
   a.plane = g.Xh * g.X[1];
   a.inv_plane = 1.0 / a.plane;
   a.inv_t = 1.0 / g.X[3];
+  a.one = 1.0f;
   const int nb = blocks_for(g.Vh << op.lg, block);
   if (op.lg > 0)
     hipLaunchKernelGGL((dslash_kernel<R, SITE, POST, G5IN, true, decltype(a)>), dim3(nb), dim3(block), 0, s, a);

@@ -673,6 +673,42 @@ __device__ __forceinline__ void project(const Spinor<R>& p, Half<R>& h) {
     }
   }
 }
+// The same projection with every sum written as a multiply-add onto a unit
+// factor `one` that the compiler cannot see is 1 (a literal 1 would be
+// simplified back to an add): the two binary16 operands of each sum then
+// convert inside one mixed-precision FMA instead of by two conversions and
+// an add.  The value is that of the plain sum.
+template <typename R, int SG>
+__device__ __forceinline__ Cx<R> proj_add(Cx<R> u, Cx<R> d, R one) {  // u + SG d
+  const R f = SG > 0 ? one : -one;
+  return {fmar(d.re, f, u.re), fmar(d.im, f, u.im)};
+}
+template <typename R, int SG>
+__device__ __forceinline__ Cx<R> proj_addi(Cx<R> u, Cx<R> d, R one) {  // u + SG i d
+  const R f = SG > 0 ? one : -one;
+  return {fmar(d.im, -f, u.re), fmar(d.re, f, u.im)};
+}
+template <int MU, int S, typename R>
+__device__ __forceinline__ void project(const Spinor<R>& p, Half<R>& h, R one) {
+  constexpr int P = S < 0 ? 1 : -1;  // sign of the first lower term
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const Cx<R> u0 = p.v[0][c], u1 = p.v[1][c], d0 = p.v[2][c], d1 = p.v[3][c];
+    if (MU == 0) {
+      h.h[0][c] = proj_addi<R, P>(u0, d1, one);
+      h.h[1][c] = proj_addi<R, P>(u1, d0, one);
+    } else if (MU == 1) {
+      h.h[0][c] = proj_add<R, P>(u0, d1, one);
+      h.h[1][c] = proj_add<R, -P>(u1, d0, one);
+    } else if (MU == 2) {
+      h.h[0][c] = proj_addi<R, P>(u0, d0, one);
+      h.h[1][c] = proj_addi<R, -P>(u1, d1, one);
+    } else {
+      h.h[0][c] = proj_add<R, -P>(u0, d0, one);
+      h.h[1][c] = proj_add<R, -P>(u1, d1, one);
+    }
+  }
+}
 // acc += (h, lower(h)) for the projector (1 + S gamma_mu)
 template <int MU, int S, typename R>
 __device__ __forceinline__ void accumulate(Spinor<R>& a, const Half<R>& h) {
