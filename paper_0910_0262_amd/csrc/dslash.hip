@@ -142,7 +142,7 @@ __device__ __forceinline__ void hop_dir(const A& a, int i, int r, const int x[4]
 // loads; halted right-hand sides keep computing with alpha = 0 (the grid
 // cannot return early for some of them).
 template <typename R, int SITE, bool POST, bool G5IN, bool MULTI, class A>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 1)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? (SITE == 2 ? 5 : 4) : 1)))
 dslash_kernel(A a) {
   if (!MULTI && a.st != nullptr && a.st->halt) return;  // uniform over the grid
   const int blk = xcd_block(blockIdx.x, gridDim.x);
