@@ -84,7 +84,7 @@ __device__ __forceinline__ void scale_half(Half<R>& h, R f) {
 // branch the FP64 kernel runs out of registers and spills.
 // i: checkerboard site (links, clover); r: right-hand side (MULTI: spinor
 // element (cb << lg) | r, otherwise cb).
-template <int MU, bool G5IN, bool MULTI, bool FUSED, typename R, class A>
+template <int MU, bool G5IN, bool MULTI, bool FUSED, bool SCALED_ACC, typename R, class A>
 __device__ __forceinline__ void hop_dir(const A& a, int i, int r, const int x[4], Spinor<R>& acc, R cu, R cl) {
   using SIn = decltype(a.in);
   constexpr bool scaled = SpinorScale<SIn>::scaled;
@@ -119,9 +119,9 @@ __device__ __forceinline__ void hop_dir(const A& a, int i, int r, const int x[4]
     project<MU, -1>(pf, h, R(a.one));
   else
     project<MU, -1>(pf, h);
-  if constexpr (!scaled && MU == 3) scale_half(h, sf);
+  if constexpr (!SCALED_ACC && MU == 3) scale_half(h, sf);
   mul_mat<FUSED>(uf, h, uh);
-  if constexpr (scaled)
+  if constexpr (SCALED_ACC)
     accumulate<MU, -1>(acc, uh, sf * cu, sf * cl);
   else
     accumulate<MU, -1>(acc, uh);
@@ -129,9 +129,9 @@ __device__ __forceinline__ void hop_dir(const A& a, int i, int r, const int x[4]
     project<MU, +1>(pb, h, R(a.one));
   else
     project<MU, +1>(pb, h);
-  if constexpr (!scaled && MU == 3) scale_half(h, sb);
+  if constexpr (!SCALED_ACC && MU == 3) scale_half(h, sb);
   mul_adj<FUSED>(ub, h, uh);
-  if constexpr (scaled)
+  if constexpr (SCALED_ACC)
     accumulate<MU, +1>(acc, uh, sb * cu, sb * cl);
   else
     accumulate<MU, +1>(acc, uh);
@@ -166,7 +166,7 @@ dslash_kernel(A a) {
     // once instead of living across the hops) and the hop scale rides on the
     // accumulating multiply-adds; with no site term and a scaled post clover
     // it joins the blocks' scales instead
-    constexpr bool SITE_FIRST = SITE != 0 && scaled;
+    constexpr bool SITE_FIRST = SITE != 0;
     constexpr bool HOP_IN_CLOVER = POST && SITE == 0 && scaled && CloverScale<decltype(a.cpost)>::scaled;
     constexpr bool HOP_IN_ACC = SITE_FIRST;
     // fused link matvecs except in the FP32 site-term kernel (k2), which
@@ -183,10 +183,11 @@ dslash_kernel(A a) {
       zero(acc);
     }
     const R hu = HOP_IN_ACC ? c : R(1), hl = HOP_IN_ACC ? cl : R(1);
-    hop_dir<0, G5IN, MULTI, FUSED>(a, i, r, x, acc, hu, hl);
-    hop_dir<1, G5IN, MULTI, FUSED>(a, i, r, x, acc, hu, hl);
-    hop_dir<2, G5IN, MULTI, FUSED>(a, i, r, x, acc, hu, hl);
-    hop_dir<3, G5IN, MULTI, FUSED>(a, i, r, x, acc, hu, hl);
+    constexpr bool SCALED_ACC = scaled || HOP_IN_ACC;
+    hop_dir<0, G5IN, MULTI, FUSED, SCALED_ACC>(a, i, r, x, acc, hu, hl);
+    hop_dir<1, G5IN, MULTI, FUSED, SCALED_ACC>(a, i, r, x, acc, hu, hl);
+    hop_dir<2, G5IN, MULTI, FUSED, SCALED_ACC>(a, i, r, x, acc, hu, hl);
+    hop_dir<3, G5IN, MULTI, FUSED, SCALED_ACC>(a, i, r, x, acc, hu, hl);
     if constexpr (!HOP_IN_CLOVER && !HOP_IN_ACC) {
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
