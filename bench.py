@@ -82,8 +82,11 @@ def spinor_bytes(prec: str) -> float:
 
 
 def k1_bytes_multi(prec: str, nr: int, mixed_clover=16) -> float:
+    """The mixed multi-source kernels read all nine binary16 link entries
+    (36 B per link) instead of two rows (24 B)."""
     sp = spinor_bytes(prec)
-    return k1_bytes_per_site(prec, mixed_clover=mixed_clover) + 2 * sp * (nr - 1)
+    links = 8 * 12 if prec == "mixed" and nr > 1 else 0
+    return k1_bytes_per_site(prec, mixed_clover=mixed_clover) + 2 * sp * (nr - 1) + links
 
 
 def k2_bytes_multi(prec: str, nr: int, mixed_clover=16) -> float:

@@ -82,6 +82,7 @@ struct qcd_ctx {
   double2* u18 = nullptr;
   double2* u12 = nullptr;
   uint2* uh = nullptr;
+  uint4* uh18 = nullptr;        // all nine entries in binary16, for the multi-source kernels
   double2* clov = nullptr;      // A, both parities: [par][36][stride]
   double2* clov_inv = nullptr;  // A_oo^{-1}: [36][stride]
   float4* clov32_e = nullptr;   // A_ee in FP32
@@ -206,6 +207,7 @@ void free_ctx(qcd_ctx* c) {
   f(c->u18);
   f(c->u12);
   f(c->uh);
+  f(c->uh18);
   f(c->clov);
   f(c->clov_inv);
   f(c->clov32_e);
@@ -296,10 +298,16 @@ ClovRef mixed_clov(const qcd_ctx* c, bool inverse_odd) {
     return inverse_odd ? ClovRef{CL_H, c->clovinvh_o, c->clovinvh_os} : ClovRef{CL_H, c->clovh_e, c->clovh_es};
   return inverse_odd ? ClovRef{CL_F32, c->clovinv32_o, nullptr} : ClovRef{CL_F32, c->clov32_e, nullptr};
 }
+// binary16 links for the mixed kernels: rows 0, 1 (row 2 rebuilt) for one
+// right-hand side, where bytes decide; all nine entries for several, where
+// the rebuild's instructions would be repeated by every right-hand side
+void mixed_links(const qcd_ctx* c, DslashOp& op) {
+  op.link_kind = c->w->lg > 0 ? LK_H18 : LK_H12;
+  op.links = c->w->lg > 0 ? (const void*)c->uh18 : (const void*)c->uh;
+}
 int k1_h(qcd_ctx* c, int in, int out, bool dag, const CgState* st) {
   DslashOp op = base_op(c, 1);
-  op.link_kind = LK_H12;
-  op.links = c->uh;
+  mixed_links(c, op);
   op.in = c->refh(in);
   op.out = c->refh(out);
   op.post = 1;
@@ -311,8 +319,7 @@ int k1_h(qcd_ctx* c, int in, int out, bool dag, const CgState* st) {
 }
 int k2_h(qcd_ctx* c, int site, int t, int out, bool dag, int epi, int y, bool a_state, const CgState* st) {
   DslashOp op = base_op(c, 0);
-  op.link_kind = LK_H12;
-  op.links = c->uh;
+  mixed_links(c, op);
   op.in = c->refh(t);
   op.site = c->refh(site);
   op.out = c->refh(out);
@@ -380,7 +387,8 @@ double mdagm_bytes_per_site(const qcd_ctx* c, bool mixed, int nr = 1) {
     const double k1 = sp + 8 * lk + cl + sp, k2 = k1 + sp;
     return 2.0 * (k1 + k2);
   }
-  const double sp = 52.0 * nr, lk = 24.0, cl = (c->mixed_clover == 16 ? 152.0 : 288.0);
+  // links: two binary16 rows for one right-hand side, all nine entries for several
+  const double sp = 52.0 * nr, lk = nr > 1 ? 36.0 : 24.0, cl = (c->mixed_clover == 16 ? 152.0 : 288.0);
   const double k1 = sp + 8 * lk + cl + sp, k2 = k1 + sp;
   return 2.0 * (k1 + k2);
 }
@@ -746,6 +754,7 @@ int qcd_create(const int dims[4], int device, uintptr_t hip_stream, qcd_ctx** ou
   A(&c->u18, 8 * 9 * S * sizeof(double2));
   A(&c->u12, 8 * 6 * S * sizeof(double2));
   A(&c->uh, 8 * 3 * S * sizeof(uint2));
+  A(&c->uh18, 8 * 2 * S * sizeof(uint4) + 8 * S * sizeof(unsigned int));
   A(&c->clov, 2 * 36 * S * sizeof(double2));
   A(&c->clov_inv, 36 * S * sizeof(double2));
   A(&c->clov32_e, 18 * S * sizeof(float4));
@@ -825,7 +834,7 @@ int qcd_load_gauge(qcd_ctx* c, const void* U_dev) {
   QCHK(check_ctx(c));
   if (!U_dev) return fail(QCD_EINVAL, "null gauge pointer");
   HIPCHK(launch_pack_gauge(c->g, (const double2*)U_dev, c->u18, c->stream));
-  HIPCHK(launch_derive_links(c->g, c->u18, c->u12, c->uh, c->stream));
+  HIPCHK(launch_derive_links(c->g, c->u18, c->u12, c->uh, c->uh18, c->stream));
   c->gauge_loaded = true;
   c->clover_ready = false;
   return QCD_OK;
@@ -1142,7 +1151,7 @@ int qcd_hmd_step(qcd_ctx* c, double dt, void* U_dev, double* P_dev, const void* 
   // U_1/2 = exp(i dt/2 P) U
   HIPCHK(launch_pack_gauge(g, (const double2*)U_dev, c->u18, c->stream));
   HIPCHK(launch_link_exp(g, c->u18, P_dev, 0.5 * dt, c->stream));
-  HIPCHK(launch_derive_links(g, c->u18, c->u12, c->uh, c->stream));
+  HIPCHK(launch_derive_links(g, c->u18, c->u12, c->uh, c->uh18, c->stream));
   c->gauge_loaded = true;
   QCHK(qcd_build_clover(c));
   // phi = Mhat^dag xi
@@ -1156,7 +1165,7 @@ int qcd_hmd_step(qcd_ctx* c, double dt, void* U_dev, double* P_dev, const void* 
   // P <- P - dt F;  U <- exp(i dt/2 P) U_1/2
   HIPCHK(launch_mom_update(g, P_dev, c->fbuf, dt, c->stream));
   HIPCHK(launch_link_exp(g, c->u18, P_dev, 0.5 * dt, c->stream));
-  HIPCHK(launch_derive_links(g, c->u18, c->u12, c->uh, c->stream));
+  HIPCHK(launch_derive_links(g, c->u18, c->u12, c->uh, c->uh18, c->stream));
   HIPCHK(launch_unpack_gauge(g, c->u18, (double2*)U_dev, c->stream));
   QCHK(qcd_build_clover(c));
   const double seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -1227,7 +1236,7 @@ int qcd_clover_det_action_force(qcd_ctx* c, double* S, void* G_dev, double* F_de
 static int move_links(qcd_ctx* c, const double* P_dev, double h, bool reunit) {
   if (h != 0.0) HIPCHK(launch_link_exp(c->g, c->u18, P_dev, h, c->stream));
   if (reunit) HIPCHK(launch_reunitarize(c->g, c->u18, c->stream));
-  HIPCHK(launch_derive_links(c->g, c->u18, c->u12, c->uh, c->stream));
+  HIPCHK(launch_derive_links(c->g, c->u18, c->u12, c->uh, c->uh18, c->stream));
   c->gauge_loaded = true;
   c->clover_ready = false;
   return QCD_OK;

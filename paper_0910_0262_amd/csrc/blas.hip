@@ -128,14 +128,14 @@ __global__ void unpack_gauge_k(Geom g, const double2* __restrict__ u18, double2*
 // FP64 12-real (first two rows) and binary16 12-real copies of the links.
 // binary16 entries are rounded float64 -> float32 -> binary16, both to nearest even.
 __global__ void derive_links_k(Geom g, const double2* __restrict__ u18, double2* __restrict__ u12,
-                               uint2* __restrict__ uh) {
+                               uint2* __restrict__ uh, uint4* __restrict__ uh18) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= 8 * g.Vh) return;
   const int q = t / g.Vh, cb = t - q * g.Vh;  // q = mu * 2 + par
   const double2* src = u18 + (size_t)(q * 9) * g.stride + cb;
-  double2 r[6];
+  double2 r[9];
 #pragma unroll
-  for (int k = 0; k < 6; ++k) r[k] = src[(size_t)k * g.stride];
+  for (int k = 0; k < 9; ++k) r[k] = src[(size_t)k * g.stride];
 #pragma unroll
   for (int k = 0; k < 6; ++k) u12[(size_t)(q * 6 + k) * g.stride + cb] = r[k];
 #pragma unroll
@@ -147,6 +147,20 @@ __global__ void derive_links_k(Geom g, const double2* __restrict__ u18, double2*
     h[3] = (_Float16)(float)r[2 * k + 1].y;
     uh[(size_t)(q * 3 + k) * g.stride + cb] = from_h4(h);
   }
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    h8_t h;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      h[2 * j] = (_Float16)(float)r[4 * k + j].x;
+      h[2 * j + 1] = (_Float16)(float)r[4 * k + j].y;
+    }
+    uh18[(size_t)(q * 2 + k) * g.stride + cb] = from_h8(h);
+  }
+  h2_t h;
+  h[0] = (_Float16)(float)r[8].x;
+  h[1] = (_Float16)(float)r[8].y;
+  ((unsigned int*)(uh18 + (size_t)16 * g.stride))[(size_t)q * g.stride + cb] = from_h2(h);
 }
 
 hipError_t launch_pack_gauge(const Geom& g, const double2* user, double2* u18, hipStream_t s) {
@@ -157,8 +171,9 @@ hipError_t launch_unpack_gauge(const Geom& g, const double2* u18, double2* user,
   hipLaunchKernelGGL(unpack_gauge_k, dim3(blocks_for(4 * g.V, 256)), dim3(256), 0, s, g, u18, user);
   return hipGetLastError();
 }
-hipError_t launch_derive_links(const Geom& g, const double2* u18, double2* u12, uint2* uh, hipStream_t s) {
-  hipLaunchKernelGGL(derive_links_k, dim3(blocks_for(8 * g.Vh, 256)), dim3(256), 0, s, g, u18, u12, uh);
+hipError_t launch_derive_links(const Geom& g, const double2* u18, double2* u12, uint2* uh, uint4* uh18,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(derive_links_k, dim3(blocks_for(8 * g.Vh, 256)), dim3(256), 0, s, g, u18, u12, uh, uh18);
   return hipGetLastError();
 }
 

@@ -14,6 +14,8 @@
 //   M:   out_p = A_pp psi_p - kappa H psi_(1-p)      (site with clover)
 //   bhat = b_e + kappa H_eo u_o, x_o = A^{-1}(b_o + kappa H_oe x_e)
 // Mhat^dag = g5 Mhat g5 uses the g5in / g5out switches.
+#include <type_traits>
+
 #include "qcd_internal.h"
 
 namespace qcd {
@@ -141,8 +143,18 @@ __device__ __forceinline__ void hop_dir(const A& a, int i, int r, const int x[4]
 // fastest, so the 1 << lg work-items of a site share its link and clover
 // loads; halted right-hand sides keep computing with alpha = 0 (the grid
 // cannot return early for some of them).
+// Wavefronts per SIMD the register allocation must leave room for: FP32
+// k1 4 (121 registers), k2 5 (96) except with an FP32 clover (which would
+// spill there); FP64 kernels take what they need (2).
+template <typename R, int SITE, class A>
+constexpr int stencil_waves() {
+  if (sizeof(R) == 8) return 1;
+  if (SITE == 2 && !std::is_same<decltype(A::cpre), CloverF32>::value) return 5;
+  return 4;
+}
+
 template <typename R, int SITE, bool POST, bool G5IN, bool MULTI, class A>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? (SITE == 2 ? 5 : 4) : 1)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(stencil_waves<R, SITE, A>())))
 dslash_kernel(A a) {
   if (!MULTI && a.st != nullptr && a.st->halt) return;  // uniform over the grid
   const int blk = xcd_block(blockIdx.x, gridDim.x);
@@ -268,6 +280,11 @@ template <>
 LinkF64<6> lk_of<LinkF64<6>>(const void* p, int stride) { return LinkF64<6>{(const double2*)p, stride}; }
 template <>
 LinkH12 lk_of<LinkH12>(const void* p, int stride) { return LinkH12{(const uint2*)p, stride}; }
+template <>
+LinkH18 lk_of<LinkH18>(const void* p, int stride) {
+  const uint4* c = (const uint4*)p;
+  return LinkH18{c, (const unsigned int*)(c + (size_t)16 * stride), stride};
+}
 
 template <typename R, class SIn, class SSite, class SOut, class LK, class CPre, class CPost, int SITE, bool POST,
           bool G5IN>
@@ -299,8 +316,11 @@ static hipError_t run_g5(const Geom& g, const DslashOp& op, int block, hipStream
   a.inv_t = 1.0 / g.X[3];
   a.one = 1.0f;
   const int nb = blocks_for(g.Vh << op.lg, block);
+  constexpr bool multi_only = std::is_same<LK, LinkH18>::value;  // 18-entry links serve the multi-source kernels
   if (op.lg > 0)
     hipLaunchKernelGGL((dslash_kernel<R, SITE, POST, G5IN, true, decltype(a)>), dim3(nb), dim3(block), 0, s, a);
+  else if constexpr (multi_only)
+    return hipErrorInvalidValue;
   else
     hipLaunchKernelGGL((dslash_kernel<R, SITE, POST, G5IN, false, decltype(a)>), dim3(nb), dim3(block), 0, s, a);
   return hipGetLastError();
@@ -326,12 +346,12 @@ static hipError_t run_f64(const Geom& g, const DslashOp& op, int block, hipStrea
   return hipErrorInvalidValue;
 }
 
-template <class CL>
+template <class CL, class LK>
 static hipError_t run_mixed(const Geom& g, const DslashOp& op, int block, hipStream_t s) {
   if (op.site_mode == 0 && op.post)
-    return run<float, SpH, SpNone, SpH, LinkH12, CloverNone, CL, 0, true>(g, op, block, s);
+    return run<float, SpH, SpNone, SpH, LK, CloverNone, CL, 0, true>(g, op, block, s);
   if (op.site_mode == 2 && !op.post)
-    return run<float, SpH, SpH, SpH, LinkH12, CL, CloverNone, 2, false>(g, op, block, s);
+    return run<float, SpH, SpH, SpH, LK, CL, CloverNone, 2, false>(g, op, block, s);
   return hipErrorInvalidValue;
 }
 
@@ -343,8 +363,13 @@ hipError_t launch_dslash(const Geom& g, const DslashOp& op, int block, hipStream
   }
   if (op.in.kind == SP_H && op.link_kind == LK_H12) {
     const int ck = op.post ? op.cpost.kind : op.cpre.kind;
-    if (ck == CL_F32) return run_mixed<CloverF32>(g, op, block, s);
-    if (ck == CL_H) return run_mixed<CloverH>(g, op, block, s);
+    if (ck == CL_F32) return run_mixed<CloverF32, LinkH12>(g, op, block, s);
+    if (ck == CL_H) return run_mixed<CloverH, LinkH12>(g, op, block, s);
+  }
+  if (op.in.kind == SP_H && op.link_kind == LK_H18 && op.lg > 0) {
+    const int ck = op.post ? op.cpost.kind : op.cpre.kind;
+    if (ck == CL_F32) return run_mixed<CloverF32, LinkH18>(g, op, block, s);
+    if (ck == CL_H) return run_mixed<CloverH, LinkH18>(g, op, block, s);
   }
   return hipErrorInvalidValue;
 }

@@ -296,6 +296,17 @@ __device__ __forceinline__ uint2 from_h4(h4_t h) {
   __builtin_memcpy(&w, &h, 8);
   return w;
 }
+typedef _Float16 h2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ h2_t as_h2(unsigned int w) {
+  h2_t h;
+  __builtin_memcpy(&h, &w, 4);
+  return h;
+}
+__device__ __forceinline__ unsigned int from_h2(h2_t h) {
+  unsigned int w;
+  __builtin_memcpy(&w, &h, 4);
+  return w;
+}
 
 // ------------------------------------------------------------------ streaming loads
 // Links and clover blocks are read once per kernel: load them nontemporally
@@ -320,6 +331,7 @@ __device__ __forceinline__ uint4 ld_stream(const uint4* p) {
   const nt_u4 v = __builtin_nontemporal_load((const nt_u4*)p);
   return make_uint4(v.x, v.y, v.z, v.w);
 }
+__device__ __forceinline__ unsigned int ld_stream(const unsigned int* p) { return __builtin_nontemporal_load(p); }
 
 // ------------------------------------------------------------------ spinor fields
 // Each field is one checkerboard, structure of arrays: component chunk k of
@@ -478,6 +490,17 @@ struct LinkH12 {   // two rows as 12 x binary16, 3 chunks of 4 halves (24 B / li
   const uint2* p;
   int stride;
 };
+// All nine entries as 18 x binary16 (36 B / link), for the multi-source
+// kernels, whose vector-instruction issue the row rebuild would cost more
+// than the 12 extra bytes (shared by all right-hand sides of a site): chunks
+// 0 and 1 (8 halves each) at p[((mu * 2 + par) * 2 + k) * stride + cb],
+// chunk 2 (the last entry) at q[(mu * 2 + par) * stride + cb]; q follows the
+// 16 * stride chunks of p in the same allocation.
+struct LinkH18 {
+  const uint4* p;
+  const unsigned int* q;
+  int stride;
+};
 
 template <typename R>
 __device__ __forceinline__ void reconstruct_row2(Mat<R>& u) {
@@ -496,6 +519,19 @@ __device__ __forceinline__ void load_link(const LinkF64<NC>& f, int mu, int par,
     u.m[k / 3][k % 3] = {R(d.x), R(d.y)};
   }
   if (NC == 6) reconstruct_row2(u);
+}
+template <typename R>
+__device__ __forceinline__ void load_link(const LinkH18& f, int mu, int par, int i, Mat<R>& u) {
+  const int d = mu * 2 + par;
+  const h8_t a = as_h8(ld_stream(f.p + (size_t)(d * 2) * f.stride + i));
+  const h8_t b = as_h8(ld_stream(f.p + (size_t)(d * 2 + 1) * f.stride + i));
+  const h2_t c = as_h2(ld_stream(f.q + (size_t)d * f.stride + i));
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    u.m[k / 3][k % 3] = {R(float(a[2 * k])), R(float(a[2 * k + 1]))};
+    u.m[(k + 4) / 3][(k + 4) % 3] = {R(float(b[2 * k])), R(float(b[2 * k + 1]))};
+  }
+  u.m[2][2] = {R(float(c[0])), R(float(c[1]))};
 }
 template <typename R>
 __device__ __forceinline__ void load_link(const LinkH12& f, int mu, int par, int i, Mat<R>& u) {

@@ -97,7 +97,7 @@ struct SpRef {
   void* p;
   float* s;  // per-site scale (SP_H)
 };
-enum LinkKind { LK_F64_18 = 0, LK_F64_12 = 1, LK_H12 = 2 };
+enum LinkKind { LK_F64_18 = 0, LK_F64_12 = 1, LK_H12 = 2, LK_H18 = 3 };
 enum ClovKind { CL_NONE = 0, CL_F64 = 1, CL_F32 = 2, CL_H = 3 };
 struct ClovRef {
   int kind;
@@ -150,7 +150,10 @@ hipError_t launch_pack_spinor_multi(const Geom& g, int lg, int n, const double2*
 hipError_t launch_unpack_spinor_multi(const Geom& g, int lg, int n, SpF64 e, SpF64 o, double2* user, hipStream_t s);
 hipError_t launch_pack_gauge(const Geom& g, const double2* user, double2* u18, hipStream_t s);
 hipError_t launch_unpack_gauge(const Geom& g, const double2* u18, double2* user, hipStream_t s);
-hipError_t launch_derive_links(const Geom& g, const double2* u18, double2* u12, uint2* uh, hipStream_t s);
+// u12: FP64 rows 0, 1; uh: binary16 rows 0, 1; uh18: all nine binary16 entries
+// (16 * stride uint4 chunks followed by 8 * stride 32-bit chunks)
+hipError_t launch_derive_links(const Geom& g, const double2* u18, double2* u12, uint2* uh, uint4* uh18,
+                               hipStream_t s);
 hipError_t launch_pack_clover(const Geom& g, const double2* user, double2* clov, hipStream_t s);
 hipError_t launch_unpack_clover(const Geom& g, const double2* clov, double2* user, int n_par, int par0,
                                 hipStream_t s);
