@@ -34,8 +34,8 @@ if ROOT not in sys.path:
 
 METRIC = "CG time-to-solution + M†M GB/s (% HBM peak), mixed vs FP64, 16^4 & 32^3x64"
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
-# FP32 vector FMA rate without packed-FP32 instructions (which this build
-# disables): 256 CUs x 64 lanes x 2 flops x 2.4 GHz
+# FP32 vector FMA rate without packed-FP32 instructions (the HIP sources are
+# compiled with them disabled): 256 CUs x 64 lanes x 2 flops x 2.4 GHz
 FP32_VALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
 FLOPS_PER_SITE = 1824.0  # 1320 hopping + 504 clover per site per M application
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k1_mixed_32x32x32x64.md")
@@ -43,7 +43,7 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k1_mixed_32x32x32x64.md")
 # k1 launch of the multi-source solve (the timed headline) and of the
 # single-source solve
 TRAFFIC_KERNELS = {
-    "k1_mixed_multi": ("dslash_kernel<float, 0, true, false, true,", "LinkH12", "CloverH>"),
+    "k1_mixed_multi": ("dslash_kernel<float, 0, true, false, true,", "LinkH18", "CloverH>"),
     "k1_mixed_single": ("dslash_kernel<float, 0, true, false, false,", "LinkH12", "CloverH>"),
 }
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_0910_0262_amd", "csrc", f) for f in ("qcd_device.h", "dslash.hip")]
@@ -323,8 +323,8 @@ def main() -> int:
         return 0
 
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md); use --gpus 1", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path; use --gpus 1",
+              file=sys.stderr)
         return 2
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)

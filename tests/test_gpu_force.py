@@ -2,7 +2,7 @@
 step against the oracle; the autograd path against the oracle and against
 central finite differences of the GPU action.
 
-Bar (BASELINE target): force relative error <= 1e-9 against the FP64 oracle,
+Bar: force relative error <= 1e-9 against the FP64 oracle,
 with the solves inside at tol 1e-12 (a solve to tol t moves the force by
 O(cond * t))."""
 import numpy as np

@@ -1,6 +1,6 @@
 """GPU parity of the even-odd solve (FP64 and mixed precision) against the oracle.
 
-Bar (BASELINE target): relative solution error <= 1e-10 against the oracle's
+Bar: relative solution error <= 1e-10 against the oracle's
 FP64 solution, both solved to tol 1e-12 (the solution error can reach
 cond(Mhat^dag Mhat) * tol); the true full-lattice residual is checked too."""
 import numpy as np
