@@ -86,9 +86,15 @@ typedef enum {
                                per-block FP32 scale (default), 32 = FP32                */
   QCD_OPT_BLOCK = 2,        /* threads per workgroup of the stencil kernels (64, 128,
                                192 or 256); 0 = 64 (default)                            */
-  QCD_OPT_GRAPH = 3         /* 1: each CG iteration is replayed as a captured HIP graph;
+  QCD_OPT_GRAPH = 3,        /* 1: each CG iteration is replayed as a captured HIP graph;
                                0 (default): its kernels are launched one by one (graph
                                replay measured no faster on MI355X)                     */
+  QCD_OPT_SMALL_GRID = 4    /* single-source stencils on lattices of at most 2^17 sites
+                               (fewer sites per checkerboard than SIMD lanes on the
+                               chip), with 64-thread workgroups: 1 (default) = two
+                               wavefronts per 64 sites (forward and backward hops split,
+                               partial sums exchanged in LDS), 0 = one work-item per
+                               site as on large lattices                                */
 } qcd_option;
 
 /* Library version, (major << 16) | minor. */

@@ -75,6 +75,7 @@ struct qcd_ctx {
   int link_recon = 12;
   int mixed_clover = 16;
   int use_graph = 0;
+  int small_grid = 1;
   int block_opt = 0;
   bool gauge_loaded = false;
   bool clover_ready = false;
@@ -256,6 +257,7 @@ DslashOp base_op(const qcd_ctx* c, int par_out) {
   op.c = 1.0;
   op.partial = c->w->partial;
   op.lg = c->w->lg;
+  op.small_grid = c->small_grid;
   return op;
 }
 
@@ -824,6 +826,10 @@ int qcd_set_option(qcd_ctx* c, int option, int value) {
     case QCD_OPT_GRAPH:
       if (value != 0 && value != 1) return fail(QCD_EINVAL, "graph option must be 0 or 1");
       c->use_graph = value;
+      return QCD_OK;
+    case QCD_OPT_SMALL_GRID:
+      if (value != 0 && value != 1) return fail(QCD_EINVAL, "small-grid option must be 0 or 1");
+      c->small_grid = value;
       return QCD_OK;
     default:
       return fail(QCD_EINVAL, "unknown option");

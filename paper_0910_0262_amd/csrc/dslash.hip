@@ -249,6 +249,230 @@ dslash_kernel(A a) {
   }
 }
 
+// ------------------------------------------------------------------ small grids: two wavefronts per 64 sites
+// Below one wavefront per SIMD, one work-item per site leaves SIMDs idle and
+// each wavefront waits out its own loads.  Here a workgroup of two
+// wavefronts takes 64 sites: wavefront 0 the four forward hops, wavefront 1
+// the four backward ones.  Each passes the partial sum of the chiral half it
+// does not keep to the other through LDS, and wavefront h then finishes
+// chiral half h (spins 2h, 2h + 1): the hop factor, its part of the site
+// term, its clover block (A is block-diagonal in the chiral halves) and its
+// half of the output.  Each branch on h is uniform within a wavefront.
+
+// Half h of a site spinor: complex components 6h .. 6h + 5.
+template <int H, typename R>
+__device__ __forceinline__ void load_half(const SpF64& f, int i, Cx<R> v[6]) {
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    const double2 d = ld_stream(f.p + (size_t)(6 * H + j) * f.stride + i);
+    v[j] = {R(d.x), R(d.y)};
+  }
+}
+// binary16 chunk k holds complex components 4k .. 4k + 3: half 0 is chunk 0
+// and the first 8 bytes of chunk 1, half 1 the last 8 bytes of chunk 1 and
+// chunk 2.
+template <int H, typename R>
+__device__ __forceinline__ void load_half(const SpH& f, int i, Cx<R> v[6]) {
+  const float s = f.s[i];
+  const h4_t m = as_h4(((const uint2*)(f.p + (size_t)f.stride + i))[H]);
+  const h8_t o = as_h8(f.p[(size_t)(2 * H) * f.stride + i]);
+#pragma unroll
+  for (int j = 0; j < 4; ++j) v[H == 0 ? j : j + 2] = {R(float(o[2 * j]) * s), R(float(o[2 * j + 1]) * s)};
+#pragma unroll
+  for (int j = 0; j < 2; ++j) v[H == 0 ? j + 4 : j] = {R(float(m[2 * j]) * s), R(float(m[2 * j + 1]) * s)};
+}
+template <typename R>
+__device__ __forceinline__ float half_max(const Cx<R> v[6]) {
+  float m = 0.f;
+#pragma unroll
+  for (int j = 0; j < 6; ++j) m = fmaxf(m, fmaxf(fabsf(float(v[j].re)), fabsf(float(v[j].im))));
+  return m;
+}
+template <int H, typename R>
+__device__ __forceinline__ void store_half(const SpF64& f, int i, const Cx<R> v[6], float) {
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    const nt_d2 w = {double(v[j].re), double(v[j].im)};
+    __builtin_nontemporal_store(w, (nt_d2*)(f.p + (size_t)(6 * H + j) * f.stride + i));
+  }
+}
+// m: the site's max |component| over both halves, as the one-work-item encoder takes it
+template <int H, typename R>
+__device__ __forceinline__ void store_half(const SpH& f, int i, const Cx<R> v[6], float m) {
+  const float inv = m > 0.f ? 1.0f / m : 0.f;
+  h8_t o;
+  h4_t q;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const Cx<R> z = v[H == 0 ? j : j + 2];
+    o[2 * j] = (_Float16)(float(z.re) * inv);
+    o[2 * j + 1] = (_Float16)(float(z.im) * inv);
+  }
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const Cx<R> z = v[H == 0 ? j + 4 : j];
+    q[2 * j] = (_Float16)(float(z.re) * inv);
+    q[2 * j + 1] = (_Float16)(float(z.im) * inv);
+  }
+  const uint4 wo = from_h8(o);
+  const uint2 wq = from_h4(q);
+  const nt_u4 no = {wo.x, wo.y, wo.z, wo.w};
+  const nt_u2 nq = {wq.x, wq.y};
+  __builtin_nontemporal_store(no, (nt_u4*)(f.p + (size_t)(2 * H) * f.stride + i));
+  __builtin_nontemporal_store(nq, (nt_u2*)(f.p + (size_t)f.stride + i) + H);
+  if (H == 1) __builtin_nontemporal_store(m, f.s + i);
+}
+
+// One hop of direction MU: S = -1 forward, (1 - gamma_mu) U_mu(x) psi(x + mu);
+// S = +1 backward, (1 + gamma_mu) U_mu(x - mu)^dag psi(x - mu).
+template <int MU, int S, bool G5IN, bool FUSED, typename R, class A>
+__device__ __forceinline__ void hop_one(const A& a, int i, const int x[4], Spinor<R>& acc) {
+  using SIn = decltype(a.in);
+  constexpr bool scaled = SpinorScale<SIn>::scaled;
+  const Geom& g = a.g;
+  int y[4] = {x[0], x[1], x[2], x[3]};
+  if (S < 0)
+    y[MU] = (x[MU] + 1 == g.X[MU]) ? 0 : x[MU] + 1;
+  else
+    y[MU] = (x[MU] == 0 ? g.X[MU] : x[MU]) - 1;
+  const int n = lex(y, g) >> 1;
+  Spinor<R> p;
+  Mat<R> u;
+  load_raw(a.in, n, p);
+  if (S < 0)
+    load_link(a.U, MU, a.par_out, i, u);
+  else
+    load_link(a.U, MU, 1 - a.par_out, n, u);
+  if constexpr (G5IN) neg_lower(p);
+  R sc = R(1);
+  if constexpr (scaled) sc = R(scale_of(a.in, n));
+  if constexpr (MU == 3) sc = (g.tb < 0 && x[3] == (S < 0 ? g.X[3] - 1 : 0)) ? -sc : sc;
+  Half<R> h, uh;
+  if constexpr (scaled)
+    project<MU, S>(p, h, R(a.one));
+  else
+    project<MU, S>(p, h);
+  if constexpr (!scaled && MU == 3) scale_half(h, sc);
+  if constexpr (S < 0)
+    mul_mat<FUSED>(u, h, uh);
+  else
+    mul_adj<FUSED>(u, h, uh);
+  if constexpr (scaled)
+    accumulate<MU, S>(acc, uh, sc, sc);
+  else
+    accumulate<MU, S>(acc, uh);
+}
+
+// Clover block H times v, times f (and the block's own scale)
+template <int H, bool FUSED, typename R, class CL>
+__device__ __forceinline__ void apply_block(const CL& c, int i, Cx<R> v[6], R f) {
+  R bs = R(1);
+  if constexpr (CloverScale<CL>::scaled) {
+    const float2 sc = block_scales(c, i);
+    bs = R(H == 0 ? sc.x : sc.y);
+  }
+  Block<R> blk;
+  load_block(c, i, H, blk);
+  block_mv<FUSED>(blk, v);
+  const R t = bs * f;
+#pragma unroll
+  for (int j = 0; j < 6; ++j) v[j] = t * v[j];
+}
+
+template <typename R>
+struct PairLds {
+  Cx<R> part[2][6][64];  // [half][component][site]: the other wavefront's partial sums
+  float m[2][64];        // per-half max |component| of a binary16 output
+};
+
+// Phase 1 of wavefront H: its four hops; hands the other half to LDS and keeps its own.
+template <int H, typename R, bool G5IN, class A>
+__device__ __forceinline__ void pair_hops(const A& a, int i, int lane, PairLds<R>& L, Cx<R> v[6]) {
+  int x[4];
+  cb_coords(i, a.par_out, a.g, x);
+  Spinor<R> acc;
+  zero(acc);
+  constexpr int S = H == 0 ? -1 : +1;
+  hop_one<0, S, G5IN, true>(a, i, x, acc);
+  hop_one<1, S, G5IN, true>(a, i, x, acc);
+  hop_one<2, S, G5IN, true>(a, i, x, acc);
+  hop_one<3, S, G5IN, true>(a, i, x, acc);
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    L.part[1 - H][j][lane] = acc.v[2 * (1 - H) + j / 3][j % 3];
+    v[j] = acc.v[2 * H + j / 3][j % 3];
+  }
+}
+
+// Phase 2 of wavefront H: the whole half, hop factor, site term, clover, epilogue value.
+template <int H, typename R, int SITE, bool POST, class A>
+__device__ __forceinline__ void pair_finish(const A& a, int i, int lane, PairLds<R>& L, Cx<R> v[6]) {
+  const R c = H == 0 ? R(a.c) : (a.g5out ? R(-a.c) : R(a.c));
+  constexpr bool FUSED_CL = sizeof(R) == 4;
+#pragma unroll
+  for (int j = 0; j < 6; ++j) v[j] = v[j] + L.part[H][j][lane];
+  if constexpr (POST && SITE == 0) {
+    apply_block<H, FUSED_CL>(a.cpost, i, v, c);
+  } else {
+#pragma unroll
+    for (int j = 0; j < 6; ++j) v[j] = c * v[j];
+    if constexpr (SITE != 0) {
+      Cx<R> sv[6];
+      load_half<H>(a.site, i, sv);
+      if constexpr (SITE == 2) apply_block<H, FUSED_CL>(a.cpre, i, sv, R(1));
+#pragma unroll
+      for (int j = 0; j < 6; ++j) v[j] = v[j] + sv[j];
+    }
+    if constexpr (POST) apply_block<H, FUSED_CL>(a.cpost, i, v, R(1));
+  }
+  if (a.epi == 2) {
+    Cx<R> yv[6];
+    load_half<H>(a.y, i, yv);
+    const R al = a.a_from_state ? R(-a.st->alpha) : R(a.a);
+#pragma unroll
+    for (int j = 0; j < 6; ++j) v[j] = yv[j] + al * v[j];
+  }
+  L.m[H][lane] = half_max(v);
+}
+
+template <typename R, int SITE, bool POST, bool G5IN, class A>
+__global__ void __launch_bounds__(128) dslash_pair_kernel(A a) {
+  if (a.st != nullptr && a.st->halt) return;  // uniform over the grid
+  __shared__ PairLds<R> L;
+  const int blk = xcd_block(blockIdx.x, gridDim.x);
+  const int lane = threadIdx.x & 63, h = threadIdx.x >> 6;
+  const int i = blk * 64 + lane;
+  const bool live = i < a.g.Vh;
+  Cx<R> v[6];
+  if (live) {
+    if (h == 0)
+      pair_hops<0, R, G5IN>(a, i, lane, L, v);
+    else
+      pair_hops<1, R, G5IN>(a, i, lane, L, v);
+  }
+  __syncthreads();
+  if (live) {
+    if (h == 0)
+      pair_finish<0, R, SITE, POST>(a, i, lane, L, v);
+    else
+      pair_finish<1, R, SITE, POST>(a, i, lane, L, v);
+  }
+  __syncthreads();
+  double nrm = 0.0;
+  if (live) {
+    const float m = fmaxf(L.m[0][lane], L.m[1][lane]);
+    if (h == 0)
+      store_half<0>(a.out, i, v, m);
+    else
+      store_half<1>(a.out, i, v, m);
+    if (a.epi >= 1) {
+#pragma unroll
+      for (int j = 0; j < 6; ++j) nrm += double(v[j].re) * double(v[j].re) + double(v[j].im) * double(v[j].im);
+    }
+  }
+  if (a.epi >= 1) block_sum_store(nrm, a.partial, blk);
+}
+
 // ------------------------------------------------------------------ dispatch
 template <class T>
 T sp_of(const SpRef& r, int stride);
@@ -286,6 +510,11 @@ LinkH18 lk_of<LinkH18>(const void* p, int stride) {
   return LinkH18{c, (const unsigned int*)(c + (size_t)16 * stride), stride};
 }
 
+// one work-item per site: up to this many sites the grid has less than one
+// wavefront per SIMD (256 CUs x 4 SIMDs x 64 lanes), and the single-source
+// stencils take two wavefronts per 64 sites instead
+constexpr int kSmallVh = 256 * 4 * 64;
+
 template <typename R, class SIn, class SSite, class SOut, class LK, class CPre, class CPost, int SITE, bool POST,
           bool G5IN>
 static hipError_t run_g5(const Geom& g, const DslashOp& op, int block, hipStream_t s) {
@@ -321,6 +550,8 @@ static hipError_t run_g5(const Geom& g, const DslashOp& op, int block, hipStream
     hipLaunchKernelGGL((dslash_kernel<R, SITE, POST, G5IN, true, decltype(a)>), dim3(nb), dim3(block), 0, s, a);
   else if constexpr (multi_only)
     return hipErrorInvalidValue;
+  else if (g.Vh <= kSmallVh && op.small_grid == 1 && block == 64)
+    hipLaunchKernelGGL((dslash_pair_kernel<R, SITE, POST, G5IN, decltype(a)>), dim3(nb), dim3(128), 0, s, a);
   else
     hipLaunchKernelGGL((dslash_kernel<R, SITE, POST, G5IN, false, decltype(a)>), dim3(nb), dim3(block), 0, s, a);
   return hipGetLastError();

@@ -130,6 +130,9 @@ struct DslashOp {
   // clover are indexed by cb and shared.  st then points at 1 << lg states
   // and the partial sums of right-hand side r start at partial[r * blocks].
   int lg;
+  // single-source kernel on small lattices: 0 one work-item per site, 1 two
+  // wavefronts per 64 sites
+  int small_grid;
 };
 
 inline int blocks_for(int n, int block) { return (n + block - 1) / block; }

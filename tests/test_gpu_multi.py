@@ -66,6 +66,36 @@ def test_multi_matches_single_and_is_deterministic(case):
     assert torch.equal(ym1, ym2)
 
 
+def test_mixed_multi_matches_single_source_mixed(case):
+    """The multi-source mixed kernels read all nine binary16 link entries, the
+    single-source ones two rows and rebuild the third: both solutions meet the
+    FP64 residual, so they agree to within cond * tol."""
+    dims, lat, setup, bs, refs = case
+    b = to_dev(bs[:3])
+    xm, sm = lat.solve_multi(b, prec="mixed", tol=1e-12)
+    for j in range(3):
+        xs, ss = lat.solve(b[j].contiguous(), prec="mixed", tol=1e-12)
+        assert rel_err(xm[j], xs) < 1e-9, j
+        assert sm[j]["true_rel_res"] < 1e-10 and ss["true_rel_res"] < 1e-10
+
+
+def test_links_rederived_after_gauge_reload():
+    """A second gauge field loaded into the same context reaches every link
+    copy the multi-source kernels read."""
+    dims, kappa, csw = (4, 4, 4, 8), 0.125, 1.0
+    lat, setup, u, ud = make_case(dims, 0.3, kappa, csw, 8)
+    bs = np.stack([synth.gaussian_source(dims, 8, j) for j in range(2)])
+    lat.solve_multi(to_dev(bs), prec="mixed", tol=1e-10)
+    u2 = synth.random_su3_field(dims, 0.4, 9)
+    lat.load_gauge(to_dev(u2))
+    setup2 = O.CloverSetup(torch.as_tensor(u2), kappa, csw)
+    x, sts = lat.solve_multi(to_dev(bs), prec="mixed", tol=1e-12)
+    for j in range(2):
+        ref = O.solve_full(setup2, torch.as_tensor(bs[j]), 1e-13).x
+        assert rel_err(x[j], ref) < 1e-10, j
+    lat.close()
+
+
 def test_zero_and_scaled_sources():
     """A zero source among others gives x = 0; sources of very different norms
     each meet the relative tolerance."""

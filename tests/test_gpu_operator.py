@@ -9,7 +9,7 @@ import torch
 
 import oracle as O
 from oracle.quant import quantize16
-from paper_0910_0262_amd import capi, synth
+from paper_0910_0262_amd import QCDError, capi, synth
 
 from ._gpu_helpers import C128, make_case, max_rel, pack_blocks, random_spinor, rel_err, to_dev
 
@@ -78,6 +78,31 @@ def test_mixed_operator_vs_oracle(case, clover_bits):
         got = lat.apply(op, to_dev(psi), prec="mixed")
         assert rel_err(got, fn(e)) < 5e-3
     lat.set_option(capi.QCD_OPT_MIXED_CLOVER, 16)
+
+
+@pytest.mark.parametrize("small_grid", [0, 1])
+def test_small_grid_forms(case, small_grid):
+    """The single-source stencil forms a small lattice can take (one work-item
+    per site, two wavefronts per 64 sites) each give the oracle's operators:
+    FP64 to rounding, mixed within the binary16 storage error; their solves
+    (norm and update epilogues) agree with the default form's to within
+    cond * tol."""
+    dims, lat, setup = case
+    lat.set_option(capi.QCD_OPT_SMALL_GRID, small_grid)
+    psi = random_spinor((setup.Vh,), 15)
+    e = torch.as_tensor(psi)
+    for op, fn in [("Mhat", setup.Mhat), ("Mhatdag", setup.Mhat_dag), ("MdagM", setup.MdagM)]:
+        assert max_rel(lat.apply(op, to_dev(psi)), fn(e)) < 1e-13, op
+        assert rel_err(lat.apply(op, to_dev(psi), prec="mixed"), fn(e)) < 5e-3, op
+    b = to_dev(synth.gaussian_source(dims, 16, 0))
+    xs = {prec: lat.solve(b, prec=prec, tol=1e-12)[0] for prec in ("fp64", "mixed")}
+    lat.set_option(capi.QCD_OPT_SMALL_GRID, 1)
+    for prec in ("fp64", "mixed"):
+        x1, st = lat.solve(b, prec=prec, tol=1e-12)
+        assert rel_err(xs[prec], x1) < 1e-9, prec
+        assert st["true_rel_res"] < 1e-10
+    with pytest.raises(QCDError, match="EINVAL"):
+        lat.set_option(capi.QCD_OPT_SMALL_GRID, 2)
 
 
 def test_encode_half_bit_exact(case):
