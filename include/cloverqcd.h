@@ -283,12 +283,13 @@ int qcd_md_trajectory(qcd_ctx *ctx, const qcd_md_params *md, void *U_dev, double
 int qcd_encode_half(qcd_ctx *ctx, int n, const void *in_dev, void *codes_dev, float *scale_dev);
 
 /* Stencil timing on the context's loaded fields and its current work
- * vectors: n (1..4096) applications of Mhat^dag Mhat (k1, k2, k1^dag, k2^dag,
- * as inside the solver) with a HIP event on the context's stream before and
- * after every launch, for prec = QCD_FP64 or QCD_MIXED.  ms[0]: average
- * launch of k1 = A_oo^{-1} H_oe psi_e (the first of the four); ms[1]: of
- * k2 = A_ee psi_e - kappa^2 H_eo t_o (the second); ms[2]: one Mhat^dag Mhat
- * (all four launches).  Milliseconds; waits for the
+ * vectors, for prec = QCD_FP64 or QCD_MIXED: n (1..4096) applications of
+ * Mhat^dag Mhat (k1, k2, k1^dag, k2^dag, as inside the solver) with a HIP
+ * event on the context's stream before and after every launch, then n more
+ * launched back to back between two events.  ms[0]: average launch of
+ * k1 = A_oo^{-1} H_oe psi_e (the first of the four); ms[1]: of
+ * k2 = A_ee psi_e - kappa^2 H_eo t_o (the second); ms[2]: one
+ * Mhat^dag Mhat from the back-to-back run.  Milliseconds; waits for the
  * work.  The vectors' contents are whatever the last operator call left
  * (timing does not depend on them). */
 int qcd_time_stencil(qcd_ctx *ctx, int prec, int n, double ms[3]);

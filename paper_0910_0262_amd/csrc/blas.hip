@@ -138,14 +138,22 @@ __global__ void derive_links_k(Geom g, const double2* __restrict__ u18, double2*
   for (int k = 0; k < 9; ++k) r[k] = src[(size_t)k * g.stride];
 #pragma unroll
   for (int k = 0; k < 6; ++k) u12[(size_t)(q * 6 + k) * g.stride + cb] = r[k];
+  {  // rows 0, 1: halves 0-7 in a 16-byte chunk, 8-11 in an 8-byte one
+    h8_t a;
+    h4_t b;
 #pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    h4_t h;
-    h[0] = (_Float16)(float)r[2 * k].x;
-    h[1] = (_Float16)(float)r[2 * k].y;
-    h[2] = (_Float16)(float)r[2 * k + 1].x;
-    h[3] = (_Float16)(float)r[2 * k + 1].y;
-    uh[(size_t)(q * 3 + k) * g.stride + cb] = from_h4(h);
+    for (int k = 0; k < 4; ++k) {
+      a[2 * k] = (_Float16)(float)r[k].x;
+      a[2 * k + 1] = (_Float16)(float)r[k].y;
+    }
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      b[2 * k] = (_Float16)(float)r[4 + k].x;
+      b[2 * k + 1] = (_Float16)(float)r[4 + k].y;
+    }
+    uint4* p4 = (uint4*)uh;
+    p4[(size_t)q * g.stride + cb] = from_h8(a);
+    ((uint2*)(p4 + (size_t)8 * g.stride))[(size_t)q * g.stride + cb] = from_h4(b);
   }
 #pragma unroll
   for (int k = 0; k < 2; ++k) {

@@ -503,7 +503,10 @@ LinkF64<9> lk_of<LinkF64<9>>(const void* p, int stride) { return LinkF64<9>{(con
 template <>
 LinkF64<6> lk_of<LinkF64<6>>(const void* p, int stride) { return LinkF64<6>{(const double2*)p, stride}; }
 template <>
-LinkH12 lk_of<LinkH12>(const void* p, int stride) { return LinkH12{(const uint2*)p, stride}; }
+LinkH12 lk_of<LinkH12>(const void* p, int stride) {
+  const uint4* c = (const uint4*)p;
+  return LinkH12{c, (const uint2*)(c + (size_t)8 * stride), stride};
+}
 template <>
 LinkH18 lk_of<LinkH18>(const void* p, int stride) {
   const uint4* c = (const uint4*)p;

@@ -486,8 +486,12 @@ struct LinkF64 {
   const double2* p;
   int stride;
 };
-struct LinkH12 {   // two rows as 12 x binary16, 3 chunks of 4 halves (24 B / link)
-  const uint2* p;
+// Two rows as 12 x binary16 (24 B / link): halves 0-7 (row 0, entry 0 of
+// row 1) at p[(mu * 2 + par) * stride + cb], halves 8-11 at q[(mu * 2 + par) *
+// stride + cb]; q follows the 8 * stride chunks of p in the same allocation.
+struct LinkH12 {
+  const uint4* p;
+  const uint2* q;
   int stride;
 };
 // All nine entries as 18 x binary16 (36 B / link), for the multi-source
@@ -535,14 +539,13 @@ __device__ __forceinline__ void load_link(const LinkH18& f, int mu, int par, int
 }
 template <typename R>
 __device__ __forceinline__ void load_link(const LinkH12& f, int mu, int par, int i, Mat<R>& u) {
-  const uint2* base = f.p + (size_t)((mu * 2 + par) * 3) * f.stride + i;
+  const int d = mu * 2 + par;
+  const h8_t a = as_h8(ld_stream(f.p + (size_t)d * f.stride + i));
+  const h4_t b = as_h4(ld_stream(f.q + (size_t)d * f.stride + i));
 #pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    h4_t h = as_h4(ld_stream(base + (size_t)k * f.stride));
-    const int c0 = 2 * k, c1 = 2 * k + 1;  // complex entries 0..5 of rows 0, 1
-    u.m[c0 / 3][c0 % 3] = {R(float(h[0])), R(float(h[1]))};
-    u.m[c1 / 3][c1 % 3] = {R(float(h[2])), R(float(h[3]))};
-  }
+  for (int k = 0; k < 4; ++k) u.m[k / 3][k % 3] = {R(float(a[2 * k])), R(float(a[2 * k + 1]))};
+  u.m[1][1] = {R(float(b[0])), R(float(b[1]))};
+  u.m[1][2] = {R(float(b[2])), R(float(b[3]))};
   reconstruct_row2(u);
 }
 
