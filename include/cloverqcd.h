@@ -196,7 +196,9 @@ int qcd_solve(qcd_ctx *ctx, const qcd_solver_params *params, const void *b_dev, 
  * n_rhs.  The first call with a given n_rhs allocates the interleaved work
  * vectors (about 12 x n_rhs' spinor fields, n_rhs' = the rounded count); they
  * are kept for later calls with as many or fewer right-hand sides.
- * QCD_ENOCONV if any right-hand side missed tol (all x are written). */
+ * QCD_EINVAL if V/2 x n_rhs' reaches 2^28 (the kernels address a field
+ * chunk with a 32-bit byte offset).  QCD_ENOCONV if any right-hand side
+ * missed tol (all x are written). */
 int qcd_solve_multi(qcd_ctx *ctx, const qcd_solver_params *params, int n_rhs, const void *b_dev, void *x_dev,
                     qcd_solver_stats *stats);
 

@@ -959,6 +959,9 @@ struct WorkGuard {
 
 // Make the multi-source work set hold 1 << lg right-hand sides.
 int use_multi(qcd_ctx* c, int lg) {
+  // the stencil addresses a chunk element with a 32-bit byte offset (16-byte elements)
+  if (((long long)c->g.stride << lg) >= (1LL << 28))
+    return fail(QCD_EINVAL, "too many interleaved right-hand sides for this lattice volume");
   if (c->wm.st == nullptr || c->wm_lg_alloc < lg) {
     free_work(c->wm);
     c->wm_lg_alloc = -1;

@@ -264,7 +264,7 @@ template <int H, typename R>
 __device__ __forceinline__ void load_half(const SpF64& f, int i, Cx<R> v[6]) {
 #pragma unroll
   for (int j = 0; j < 6; ++j) {
-    const double2 d = ld_stream(f.p + (size_t)(6 * H + j) * f.stride + i);
+    const double2 d = ld_stream(elem(f.p, (size_t)(6 * H + j) * f.stride, i));
     v[j] = {R(d.x), R(d.y)};
   }
 }
@@ -273,9 +273,9 @@ __device__ __forceinline__ void load_half(const SpF64& f, int i, Cx<R> v[6]) {
 // chunk 2.
 template <int H, typename R>
 __device__ __forceinline__ void load_half(const SpH& f, int i, Cx<R> v[6]) {
-  const float s = f.s[i];
-  const h4_t m = as_h4(((const uint2*)(f.p + (size_t)f.stride + i))[H]);
-  const h8_t o = as_h8(f.p[(size_t)(2 * H) * f.stride + i]);
+  const float s = *elem(f.s, 0, i);
+  const h4_t m = as_h4(((const uint2*)elem(f.p, (size_t)f.stride, i))[H]);
+  const h8_t o = as_h8(*elem(f.p, (size_t)(2 * H) * f.stride, i));
 #pragma unroll
   for (int j = 0; j < 4; ++j) v[H == 0 ? j : j + 2] = {R(float(o[2 * j]) * s), R(float(o[2 * j + 1]) * s)};
 #pragma unroll
@@ -293,7 +293,7 @@ __device__ __forceinline__ void store_half(const SpF64& f, int i, const Cx<R> v[
 #pragma unroll
   for (int j = 0; j < 6; ++j) {
     const nt_d2 w = {double(v[j].re), double(v[j].im)};
-    __builtin_nontemporal_store(w, (nt_d2*)(f.p + (size_t)(6 * H + j) * f.stride + i));
+    __builtin_nontemporal_store(w, (nt_d2*)elem(f.p, (size_t)(6 * H + j) * f.stride, i));
   }
 }
 // m: the site's max |component| over both halves, as the one-work-item encoder takes it
@@ -318,9 +318,9 @@ __device__ __forceinline__ void store_half(const SpH& f, int i, const Cx<R> v[6]
   const uint2 wq = from_h4(q);
   const nt_u4 no = {wo.x, wo.y, wo.z, wo.w};
   const nt_u2 nq = {wq.x, wq.y};
-  __builtin_nontemporal_store(no, (nt_u4*)(f.p + (size_t)(2 * H) * f.stride + i));
-  __builtin_nontemporal_store(nq, (nt_u2*)(f.p + (size_t)f.stride + i) + H);
-  if (H == 1) __builtin_nontemporal_store(m, f.s + i);
+  __builtin_nontemporal_store(no, (nt_u4*)elem(f.p, (size_t)(2 * H) * f.stride, i));
+  __builtin_nontemporal_store(nq, (nt_u2*)elem(f.p, (size_t)f.stride, i) + H);
+  if (H == 1) __builtin_nontemporal_store(m, elem(f.s, 0, i));
 }
 
 // One hop of direction MU: S = -1 forward, (1 - gamma_mu) U_mu(x) psi(x + mu);

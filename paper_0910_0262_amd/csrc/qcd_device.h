@@ -308,6 +308,24 @@ __device__ __forceinline__ unsigned int from_h2(h2_t h) {
   return w;
 }
 
+// ------------------------------------------------------------------ field addressing
+// Element i of chunk k of a structure-of-arrays field (chunk k starts at
+// p + k * stride): the chunk base is the same for the whole grid and i is a
+// 32-bit index, so the compiler issues a load with a scalar 64-bit base and a
+// 32-bit per-lane byte offset instead of building a 64-bit address per lane
+// (fewer vector instructions and registers).  The host keeps every index
+// times 16 below 2^32.
+template <class T>
+__device__ __forceinline__ T* elem(T* p, size_t chunk_off, int i) {
+  char* base = (char*)(p + chunk_off);
+  return (T*)(base + (unsigned)i * (unsigned)sizeof(T));
+}
+template <class T>
+__device__ __forceinline__ const T* elem(const T* p, size_t chunk_off, int i) {
+  const char* base = (const char*)(p + chunk_off);
+  return (const T*)(base + (unsigned)i * (unsigned)sizeof(T));
+}
+
 // ------------------------------------------------------------------ streaming loads
 // Links and clover blocks are read once per kernel: load them nontemporally
 // so the caches keep the neighbour spinors, which are read up to 8 times.
@@ -355,7 +373,7 @@ template <typename R>
 __device__ __forceinline__ void load(const SpF64& f, int i, Spinor<R>& v) {
 #pragma unroll
   for (int k = 0; k < 12; ++k) {
-    double2 d = f.p[(size_t)k * f.stride + i];
+    double2 d = *elem(f.p, (size_t)k * f.stride, i);
     v.v[k / 3][k % 3] = {R(d.x), R(d.y)};
   }
 }
@@ -367,7 +385,7 @@ __device__ __forceinline__ void store(const SpF64& f, int i, const Spinor<R>& v)
 #pragma unroll
   for (int k = 0; k < 12; ++k) {
     const nt_d2 w = {double(v.v[k / 3][k % 3].re), double(v.v[k / 3][k % 3].im)};
-    __builtin_nontemporal_store(w, (nt_d2*)(f.p + (size_t)k * f.stride + i));
+    __builtin_nontemporal_store(w, (nt_d2*)elem(f.p, (size_t)k * f.stride, i));
   }
 }
 // Site-local spinor read once per kernel (the k2 site term, the epilogue's y).
@@ -375,7 +393,7 @@ template <typename R>
 __device__ __forceinline__ void load_once(const SpF64& f, int i, Spinor<R>& v) {
 #pragma unroll
   for (int k = 0; k < 12; ++k) {
-    const double2 d = ld_stream(f.p + (size_t)k * f.stride + i);
+    const double2 d = ld_stream(elem(f.p, (size_t)k * f.stride, i));
     v.v[k / 3][k % 3] = {R(d.x), R(d.y)};
   }
 }
@@ -383,7 +401,7 @@ template <typename R>
 __device__ __forceinline__ void load(const SpF32& f, int i, Spinor<R>& v) {
 #pragma unroll
   for (int k = 0; k < 6; ++k) {
-    float4 d = f.p[(size_t)k * f.stride + i];
+    float4 d = *elem(f.p, (size_t)k * f.stride, i);
     v.v[(2 * k) / 3][(2 * k) % 3] = {R(d.x), R(d.y)};
     v.v[(2 * k + 1) / 3][(2 * k + 1) % 3] = {R(d.z), R(d.w)};
   }
@@ -393,7 +411,7 @@ __device__ __forceinline__ void store(const SpF32& f, int i, const Spinor<R>& v)
 #pragma unroll
   for (int k = 0; k < 6; ++k) {
     const Cx<R> a = v.v[(2 * k) / 3][(2 * k) % 3], b = v.v[(2 * k + 1) / 3][(2 * k + 1) % 3];
-    f.p[(size_t)k * f.stride + i] = make_float4(float(a.re), float(a.im), float(b.re), float(b.im));
+    *elem(f.p, (size_t)k * f.stride, i) = make_float4(float(a.re), float(a.im), float(b.re), float(b.im));
   }
 }
 // Neighbour loads in the stencil: the components as stored, with the
@@ -415,7 +433,7 @@ template <typename R>
 __device__ __forceinline__ void load_raw(const SpH& f, int i, Spinor<R>& v) {
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    h8_t h = as_h8(f.p[(size_t)k * f.stride + i]);
+    h8_t h = as_h8(*elem(f.p, (size_t)k * f.stride, i));
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int c = 4 * k + j;
@@ -423,19 +441,20 @@ __device__ __forceinline__ void load_raw(const SpH& f, int i, Spinor<R>& v) {
     }
   }
 }
-__device__ __forceinline__ float scale_of(const SpH& f, int i) { return f.s[i]; }
+__device__ __forceinline__ float scale_of(const SpH& f, int i) { return *elem(f.s, 0, i); }
 __device__ __forceinline__ float scale_of(const SpF64&, int) { return 1.0f; }
 
 template <typename R>
 __device__ __forceinline__ void load(const SpH& f, int i, Spinor<R>& v) {
-  const float s = f.s[i];
+  const float s = *elem(f.s, 0, i);
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    h8_t h = as_h8(f.p[(size_t)k * f.stride + i]);
+    h8_t h = as_h8(*elem(f.p, (size_t)k * f.stride, i));
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int c = 4 * k + j;  // complex component 0..11
-      v.v[c / 3][c % 3] = {R(float(h[2 * j]) * s), R(float(h[2 * j + 1]) * s)};
+      // code * scale as an FMA onto +0: the binary16 code converts inside it
+      v.v[c / 3][c % 3] = {R(fmar(float(h[2 * j]), s, 0.f)), R(fmar(float(h[2 * j + 1]), s, 0.f))};
     }
   }
 }
@@ -468,9 +487,9 @@ __device__ __forceinline__ void store(const SpH& f, int i, const Spinor<R>& v) {
   for (int k = 0; k < 3; ++k) {
     const uint4 w = from_h8(h[k]);
     const nt_u4 q = {w.x, w.y, w.z, w.w};
-    __builtin_nontemporal_store(q, (nt_u4*)(f.p + (size_t)k * f.stride + i));
+    __builtin_nontemporal_store(q, (nt_u4*)elem(f.p, (size_t)k * f.stride, i));
   }
-  __builtin_nontemporal_store(m, f.s + i);
+  __builtin_nontemporal_store(m, elem(f.s, 0, i));
 }
 // binary16 site spinors are small enough to stay cache-resident: plain loads
 template <typename R>
@@ -516,10 +535,9 @@ __device__ __forceinline__ void reconstruct_row2(Mat<R>& u) {
 }
 template <typename R, int NC>
 __device__ __forceinline__ void load_link(const LinkF64<NC>& f, int mu, int par, int i, Mat<R>& u) {
-  const double2* base = f.p + (size_t)((mu * 2 + par) * NC) * f.stride + i;
 #pragma unroll
   for (int k = 0; k < NC; ++k) {
-    double2 d = ld_stream(base + (size_t)k * f.stride);
+    double2 d = ld_stream(elem(f.p, (size_t)((mu * 2 + par) * NC + k) * f.stride, i));
     u.m[k / 3][k % 3] = {R(d.x), R(d.y)};
   }
   if (NC == 6) reconstruct_row2(u);
@@ -527,9 +545,9 @@ __device__ __forceinline__ void load_link(const LinkF64<NC>& f, int mu, int par,
 template <typename R>
 __device__ __forceinline__ void load_link(const LinkH18& f, int mu, int par, int i, Mat<R>& u) {
   const int d = mu * 2 + par;
-  const h8_t a = as_h8(ld_stream(f.p + (size_t)(d * 2) * f.stride + i));
-  const h8_t b = as_h8(ld_stream(f.p + (size_t)(d * 2 + 1) * f.stride + i));
-  const h2_t c = as_h2(ld_stream(f.q + (size_t)d * f.stride + i));
+  const h8_t a = as_h8(ld_stream(elem(f.p, (size_t)(d * 2) * f.stride, i)));
+  const h8_t b = as_h8(ld_stream(elem(f.p, (size_t)(d * 2 + 1) * f.stride, i)));
+  const h2_t c = as_h2(ld_stream(elem(f.q, (size_t)d * f.stride, i)));
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     u.m[k / 3][k % 3] = {R(float(a[2 * k])), R(float(a[2 * k + 1]))};
@@ -540,8 +558,8 @@ __device__ __forceinline__ void load_link(const LinkH18& f, int mu, int par, int
 template <typename R>
 __device__ __forceinline__ void load_link(const LinkH12& f, int mu, int par, int i, Mat<R>& u) {
   const int d = mu * 2 + par;
-  const h8_t a = as_h8(ld_stream(f.p + (size_t)d * f.stride + i));
-  const h4_t b = as_h4(ld_stream(f.q + (size_t)d * f.stride + i));
+  const h8_t a = as_h8(ld_stream(elem(f.p, (size_t)d * f.stride, i)));
+  const h4_t b = as_h4(ld_stream(elem(f.q, (size_t)d * f.stride, i)));
 #pragma unroll
   for (int k = 0; k < 4; ++k) u.m[k / 3][k % 3] = {R(float(a[2 * k])), R(float(a[2 * k + 1]))};
   u.m[1][1] = {R(float(b[0])), R(float(b[1]))};
@@ -578,16 +596,15 @@ struct Block {
 
 template <typename R>
 __device__ __forceinline__ void load_block(const CloverF64& c, int i, int b, Block<R>& blk) {
-  const double2* base = c.p + (size_t)(b * 18) * c.stride + i;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    double2 d = ld_stream(base + (size_t)k * c.stride);
+    double2 d = ld_stream(elem(c.p, (size_t)(b * 18 + k) * c.stride, i));
     blk.d[2 * k] = R(d.x);
     blk.d[2 * k + 1] = R(d.y);
   }
 #pragma unroll
   for (int k = 0; k < 15; ++k) {
-    double2 d = ld_stream(base + (size_t)(3 + k) * c.stride);
+    double2 d = ld_stream(elem(c.p, (size_t)(b * 18 + 3 + k) * c.stride, i));
     blk.o[k] = {R(d.x), R(d.y)};
   }
 }
@@ -596,7 +613,7 @@ __device__ __forceinline__ void load_block(const CloverF32& c, int i, int b, Blo
   float r[36];
 #pragma unroll
   for (int k = 0; k < 9; ++k) {
-    float4 d = ld_stream(c.p + (size_t)(b * 9 + k) * c.stride + i);
+    float4 d = ld_stream(elem(c.p, (size_t)(b * 9 + k) * c.stride, i));
     r[4 * k] = d.x;
     r[4 * k + 1] = d.y;
     r[4 * k + 2] = d.z;
@@ -619,7 +636,7 @@ __device__ __forceinline__ void load_block(const CloverH& c, int i, int b, Block
   for (int k = 0; k < 9; ++k) {
     const int lo = 8 * k, hi = 8 * k + 8;  // half indices of this chunk
     if (hi <= 36 * b || lo >= 36 * b + 36) continue;
-    h8_t h = as_h8(ld_stream(c.p + (size_t)k * c.stride + i));
+    h8_t h = as_h8(ld_stream(elem(c.p, (size_t)k * c.stride, i)));
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const int q = lo + j - 36 * b;
@@ -639,7 +656,7 @@ template <>
 struct CloverScale<CloverH> {
   static constexpr bool scaled = true;
 };
-__device__ __forceinline__ float2 block_scales(const CloverH& c, int i) { return c.s[i]; }
+__device__ __forceinline__ float2 block_scales(const CloverH& c, int i) { return *elem(c.s, 0, i); }
 
 // v <- A v for one 6-vector (spins 2b, 2b+1).  FUSED: each row as one chain
 // of fused multiply-adds (with binary16 entries the conversion folds into
