@@ -12,7 +12,7 @@ import pytest
 import torch
 
 import oracle as O
-from paper_0910_0262_amd import Lattice, QCDError, synth
+from paper_0910_0262_amd import Lattice, QCDError, capi, synth
 
 from ._gpu_helpers import make_case, rel_err, to_dev
 
@@ -77,6 +77,19 @@ def test_mixed_multi_matches_single_source_mixed(case):
         xs, ss = lat.solve(b[j].contiguous(), prec="mixed", tol=1e-12)
         assert rel_err(xm[j], xs) < 1e-9, j
         assert sm[j]["true_rel_res"] < 1e-10 and ss["true_rel_res"] < 1e-10
+
+
+def test_multi_with_fp32_clover(case):
+    """The multi-source mixed kernels with the FP32 clover storage option."""
+    dims, lat, setup, bs, refs = case
+    lat.set_option(capi.QCD_OPT_MIXED_CLOVER, 32)
+    try:
+        x, sts = lat.solve_multi(to_dev(bs[:3]), prec="mixed", tol=1e-12)
+    finally:
+        lat.set_option(capi.QCD_OPT_MIXED_CLOVER, 16)
+    for j in range(3):
+        assert sts[j]["converged"] == 1
+        assert rel_err(x[j], refs[j]) < 1e-10, j
 
 
 def test_links_rederived_after_gauge_reload():
