@@ -262,7 +262,16 @@ DslashOp base_op(const qcd_ctx* c, int par_out) {
 }
 
 // t_o = A_oo^{-1} g5^dag H_oe g5^dag in_e   (dag: g5 on input and output of the hop)
-int k1_f64(qcd_ctx* c, int in, int out, bool dag, const CgState* st) {
+// k1 that also finishes alpha from the work set's partials (in place of a
+// finalisation launch): only for the dagger k1 of a CG iteration, which does
+// not itself read alpha
+void fuse_fin_alpha(const qcd_ctx* c, DslashOp& op) {
+  op.fin_st = c->w->st;
+  op.fin_partial = c->w->partial;
+  op.fin_n = blocks_for(c->w->gv.Vh, c->block());  // the partials of the previous launch
+  op.fin_nr = c->w->nr;
+}
+int k1_f64(qcd_ctx* c, int in, int out, bool dag, const CgState* st, bool fin_alpha = false) {
   DslashOp op = base_op(c, 1);
   op.in = c->ref64(in);
   op.out = c->ref64(out);
@@ -272,6 +281,7 @@ int k1_f64(qcd_ctx* c, int in, int out, bool dag, const CgState* st) {
   op.g5in = dag;
   op.g5out = 0;
   op.st = st;
+  if (fin_alpha) fuse_fin_alpha(c, op);
   HIPCHK(launch_dslash(c->g, op, c->block(), c->stream));
   return QCD_OK;
 }
@@ -307,7 +317,7 @@ void mixed_links(const qcd_ctx* c, DslashOp& op) {
   op.link_kind = c->w->lg > 0 ? LK_H18 : LK_H12;
   op.links = c->w->lg > 0 ? (const void*)c->uh18 : (const void*)c->uh;
 }
-int k1_h(qcd_ctx* c, int in, int out, bool dag, const CgState* st) {
+int k1_h(qcd_ctx* c, int in, int out, bool dag, const CgState* st, bool fin_alpha = false) {
   DslashOp op = base_op(c, 1);
   mixed_links(c, op);
   op.in = c->refh(in);
@@ -316,6 +326,7 @@ int k1_h(qcd_ctx* c, int in, int out, bool dag, const CgState* st) {
   op.cpost = mixed_clov(c, true);
   op.g5in = dag;
   op.st = st;
+  if (fin_alpha) fuse_fin_alpha(c, op);
   HIPCHK(launch_dslash(c->g, op, c->block(), c->stream));
   return QCD_OK;
 }
@@ -478,27 +489,35 @@ int init_recurrence(qcd_ctx* c, double tol, double delta, int max_iter, int mixe
   return wait_slot(c, slot, posted);
 }
 
+// Partials per right-hand side up to which the dagger k1 finishes alpha itself.
+constexpr int kFuseFinPartials = 1024;
+
 // The kernels of one CG iteration (they read alpha, beta and the halt flag
 // from the device state, so the sequence is the same every iteration).
 int launch_iter(qcd_ctx* c, bool mixed) {
   const int nb = nblocks(c);
-  // The reductions are finished by one-workgroup kernels.  (Finishing them
-  // inside the stencil kernels with a last-workgroup-arrives scheme needs a
-  // device-scope fence per workgroup, which writes back the XCD's L2 on this
-  // GPU and made the iteration three times slower.)
+  // The reductions are finished by one-workgroup kernels, except that on
+  // small lattices (launch-bound: a launch costs a few microseconds) the first
+  // workgroups of the dagger k1, which does not read alpha, finish it; with
+  // many partials per right-hand side those workgroups would outlast the
+  // stencil.  (Finishing a reduction inside the stencil that produces it,
+  // with a last-workgroup-arrives scheme, needs a device-scope fence per
+  // workgroup, which writes back the XCD's L2 on this GPU and made the
+  // iteration three times slower.)
+  const bool fuse = nb <= kFuseFinPartials;
   if (!mixed) {
     QCHK(k1_f64(c, V_P, V_T, false, c->w->st));
     QCHK(k2_f64(c, V_P, V_T, V_Q, false, 1, 0, 0.0, false, c->w->st));
-    HIPCHK(launch_fin_alpha(c->w->st, c->w->partial, nb, c->w->nr, c->stream));
-    QCHK(k1_f64(c, V_Q, V_T, true, c->w->st));
+    if (!fuse) HIPCHK(launch_fin_alpha(c->w->st, c->w->partial, nb, c->w->nr, c->stream));
+    QCHK(k1_f64(c, V_Q, V_T, true, c->w->st, fuse));
     QCHK(k2_f64(c, V_Q, V_T, V_R, true, 2, V_R, 0.0, true, c->w->st));
     HIPCHK(launch_fin_beta(c->w->st, c->w->partial, nb, c->w->nr, c->w->mbox_dev, kRing, c->stream));
     HIPCHK(launch_xp_update_f64(c->w->gv, c->w->lg, c->w->st, c->f64(V_X), c->f64(V_P), c->f64(V_R), c->block(), c->stream));
   } else {
     QCHK(k1_h(c, H_P, H_T, false, c->w->st));
     QCHK(k2_h(c, H_P, H_T, H_Q, false, 1, 0, false, c->w->st));
-    HIPCHK(launch_fin_alpha(c->w->st, c->w->partial, nb, c->w->nr, c->stream));
-    QCHK(k1_h(c, H_Q, H_T, true, c->w->st));
+    if (!fuse) HIPCHK(launch_fin_alpha(c->w->st, c->w->partial, nb, c->w->nr, c->stream));
+    QCHK(k1_h(c, H_Q, H_T, true, c->w->st, fuse));
     QCHK(k2_h(c, H_Q, H_T, H_R, true, 2, H_R, true, c->w->st));
     HIPCHK(launch_fin_beta(c->w->st, c->w->partial, nb, c->w->nr, c->w->mbox_dev, kRing, c->stream));
     HIPCHK(launch_xp_update_h(c->w->gv, c->w->lg, c->w->st, c->f32(), c->h(H_P), c->h(H_R), c->block(), c->stream));

@@ -45,7 +45,22 @@ struct DArgs {
   int tile_lg, plane;  // plane = (Lx / 2) Ly checkerboard sites per z-t plane
   double inv_plane, inv_t;
   float one;  // 1, opaque to the compiler (see project())
+  CgState* fin_st;  // see DslashOp
+  const double* fin_partial;
+  int fin_n, fin_nr;
 };
+
+// Workgroups r < fin_nr finish alpha for right-hand side r (the sums of the
+// previous launch's |Mhat p|^2 partials), in the finalisation kernel's own
+// fixed order; whole workgroups take the same branch.
+template <class A>
+__device__ __forceinline__ void fused_fin_alpha(const A& a) {
+  if ((int)blockIdx.x >= a.fin_nr) return;
+  CgState* st = a.fin_st + blockIdx.x;
+  if (st->halt) return;
+  const double qq = block_sum_partials(a.fin_partial + (size_t)blockIdx.x * a.fin_n, a.fin_n);
+  if (threadIdx.x == 0) state_alpha(st, qq);
+}
 
 // Site of the multi-source kernel's j-th work position.  The sites are taken
 // in xy-planes, then z within a tile of 1 << tile_lg planes, then t, then
@@ -156,6 +171,7 @@ constexpr int stencil_waves() {
 template <typename R, int SITE, bool POST, bool G5IN, bool MULTI, class A>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(stencil_waves<R, SITE, A>())))
 dslash_kernel(A a) {
+  if (a.fin_nr > 0) fused_fin_alpha(a);
   if (!MULTI && a.st != nullptr && a.st->halt) return;  // uniform over the grid
   const int blk = xcd_block(blockIdx.x, gridDim.x);
   const int w = blk * blockDim.x + threadIdx.x;  // work position
@@ -437,6 +453,7 @@ __device__ __forceinline__ void pair_finish(const A& a, int i, int lane, PairLds
 
 template <typename R, int SITE, bool POST, bool G5IN, class A>
 __global__ void __launch_bounds__(128) dslash_pair_kernel(A a) {
+  if (a.fin_nr > 0) fused_fin_alpha(a);
   if (a.st != nullptr && a.st->halt) return;  // uniform over the grid
   __shared__ PairLds<R> L;
   const int blk = xcd_block(blockIdx.x, gridDim.x);
@@ -547,6 +564,10 @@ static hipError_t run_g5(const Geom& g, const DslashOp& op, int block, hipStream
   a.inv_plane = 1.0 / a.plane;
   a.inv_t = 1.0 / g.X[3];
   a.one = 1.0f;
+  a.fin_st = op.fin_st;
+  a.fin_partial = op.fin_partial;
+  a.fin_n = op.fin_n;
+  a.fin_nr = op.fin_nr;
   const int nb = blocks_for(g.Vh << op.lg, block);
   constexpr bool multi_only = std::is_same<LK, LinkH18>::value;  // 18-entry links serve the multi-source kernels
   if (op.lg > 0)

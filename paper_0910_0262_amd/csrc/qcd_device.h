@@ -865,6 +865,8 @@ __device__ __forceinline__ void block_sum_store_seg(double v, double* partial, i
 // every thread.  Deterministic for a given n and blockDim.
 __device__ __forceinline__ double block_sum_partials(const double* p, int n) {
   double s = 0.0;
+  // unrolled so that several loads are in flight; the additions keep their order
+#pragma unroll 8
   for (int k = threadIdx.x; k < n; k += blockDim.x) s += p[k];
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);

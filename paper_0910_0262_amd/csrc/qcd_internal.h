@@ -133,6 +133,13 @@ struct DslashOp {
   // single-source kernel on small lattices: 0 one work-item per site, 1 two
   // wavefronts per 64 sites
   int small_grid;
+  // fin_nr > 0: before its stencil work, workgroup r < fin_nr of the launch
+  // finishes alpha for right-hand side r, exactly as the finalisation kernel
+  // would (fin_st[r], the fin_n partials at fin_partial + r * fin_n); the
+  // launch must not itself read alpha
+  CgState* fin_st;
+  const double* fin_partial;
+  int fin_n, fin_nr;
 };
 
 inline int blocks_for(int n, int block) { return (n + block - 1) / block; }
