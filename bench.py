@@ -38,11 +38,12 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 # compiled with them disabled): 256 CUs x 64 lanes x 2 flops x 2.4 GHz
 FP32_VALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
 FLOPS_PER_SITE = 1824.0  # 1320 hopping + 504 clover per site per M application
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k1_mixed_32x32x32x64.md")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_dslash_mixed_32x32x32x64.md")
 # kernels whose HBM traffic the committed counter summary records: the mixed
-# k1 launch of the multi-source solve (the timed headline) and of the
-# single-source solve
+# k2 and k1 launches of the multi-source solve (the timed headline) and the
+# mixed k1 of the single-source solve
 TRAFFIC_KERNELS = {
+    "k2_mixed_multi": ("dslash_kernel<float, 2, false, false, true,", "LinkH18, qcd::CloverH,"),
     "k1_mixed_multi": ("dslash_kernel<float, 0, true, false, true,", "LinkH18", "CloverH>"),
     "k1_mixed_single": ("dslash_kernel<float, 0, true, false, false,", "LinkH12", "CloverH>"),
 }
@@ -138,7 +139,8 @@ def traffic_summary(fetch_csv: str, write_csv: str, vh: int, command: str, nr: i
     w_c, _ = mean_of(wr, ("stream_copy_k",))
     copy_bytes = float(2 << 30)
     fs, ws = copy_bytes / (f_c * 1024.0), copy_bytes / (w_c * 1024.0)
-    alg = {"k1_mixed_multi": k1_bytes_multi("mixed", nr) * vh, "k1_mixed_single": k1_bytes_per_site("mixed") * vh}
+    alg = {"k2_mixed_multi": k2_bytes_multi("mixed", nr) * vh, "k1_mixed_multi": k1_bytes_multi("mixed", nr) * vh,
+           "k1_mixed_single": k1_bytes_per_site("mixed") * vh}
     kernels = {}
     for key, tokens in TRAFFIC_KERNELS.items():
         f_k, n_f = mean_of(fr, tokens)
@@ -150,7 +152,7 @@ def traffic_summary(fetch_csv: str, write_csv: str, vh: int, command: str, nr: i
     rec = {"vh": vh, "nr_multi": nr, "copy_fetch_kib": f_c, "copy_write_kib": w_c, "copy_bytes": copy_bytes,
            "fetch_scale": fs, "write_scale": ws, "kernels": kernels, "source_sha256": kernel_source_hash()}
     with open(TRAFFIC_FILE, "w") as f:
-        f.write("# HBM traffic of the mixed k1 stencil at 32x32x32x64 (rocprofv3 counters)\n\n")
+        f.write("# HBM traffic of the mixed stencils at 32x32x32x64 (rocprofv3 counters)\n\n")
         f.write("Two counter passes over the same command, run from the repository root on one MI355X:\n\n")
         f.write("```\n" + command + "\n```\n\n")
         f.write(f"FETCH_SIZE reads {f_c:.0f} KiB and WRITE_SIZE {w_c:.0f} KiB per dispatch of the 2 GiB copy "
@@ -457,31 +459,42 @@ def main() -> int:
     mdagm = {p: stencil_summary(np.mean(np.array(rec["stencil"][p]), axis=0), p, 1) for p in ("mixed", "fp64")}
     mdagm_multi = ({p: stencil_summary(np.mean(np.array(rec["stencil_multi"][p]), axis=0), p, NR)
                     for p in ("mixed", "fp64")} if NR > 1 else None)
-    # roofline: the mixed k1 launch of the timed (multi-source) solve.  With 8
-    # sources sharing each link and clover load the kernel is bound by vector
-    # instruction issue (counters: about 94 % of VALU cycles busy), not HBM, so
-    # it is placed against the FP32 FMA peak; its HBM rate is reported beside.
-    # With one source it is HBM-bound.
+    # roofline: the dominant kernel of the timed (multi-source) solve, the
+    # mixed k2 (with k2^dag, 326 of the solve's launches against 163 + 163 for
+    # k1 and k1^dag).  With 8 sources sharing each link and clover load it is
+    # bound by vector instruction issue (counters: over 80 % of the VALU issue
+    # capacity), not HBM, so it is placed against the FP32 FMA peak; its HBM
+    # rate is reported beside.  The mixed k1 of the same solve follows as
+    # roofline_k1_multi.  With one source the kernels are HBM-bound.
     head = mdagm_multi["mixed"] if NR > 1 else mdagm["mixed"]
-    k1_bytes = k1_bytes_multi("mixed", NR, mc) * Vh
-    k1_flops = FLOPS_PER_SITE * Vh * NR
-    k1_s = head["k1_ms"] * 1e-3
-    tkey = "k1_mixed_multi" if NR > 1 else "k1_mixed_single"
-    traffic = traffic_for(tkey, Vh) if (mc == 16 and (NR == 8 or NR == 1)) else None
-    kname = ("dslash_kernel<float, 0, true, false, " + ("true" if NR > 1 else "false") +
-             f", ...CloverH> (mixed k1: t_o = A_oo^-1 H_oe p_e for {NR} interleaved sources, binary16 "
-             f"spinors/links, {'FP32' if mc == 32 else 'binary16'} clover)")
-    if NR > 1:
-        achieved = k1_flops / k1_s / 1e12
-        roofline = {"bound": "alu", "achieved": achieved, "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+    clover_name = "FP32" if mc == 32 else "binary16"
+
+    def alu_or_hbm(which: str):
+        k = "k2" if which == "k2" else "k1"
+        if NR > 1:
+            nbytes = (k2_bytes_multi if k == "k2" else k1_bytes_multi)("mixed", NR, mc) * Vh
+        else:
+            nbytes = (k2_bytes_per_site if k == "k2" else k1_bytes_per_site)("mixed", mixed_clover=mc) * Vh
+        flops = FLOPS_PER_SITE * Vh * NR
+        secs = head[k + "_ms"] * 1e-3
+        tkey = f"{k}_mixed_{'multi' if NR > 1 else 'single'}"
+        traffic = traffic_for(tkey, Vh) if (mc == 16 and (NR == 8 or NR == 1)) else None
+        what = ("k2: A_ee p_e - kappa^2 H_eo t_o" if k == "k2" else "k1: t_o = A_oo^-1 H_oe p_e")
+        kname = (f"dslash_kernel<float, {2 if k == 'k2' else 0}, {'false' if k == 'k2' else 'true'}, false, "
+                 f"{'true' if NR > 1 else 'false'}, ...> (mixed {what} for {NR} interleaved sources, binary16 "
+                 f"spinors/links, {clover_name} clover)")
+        if NR > 1:
+            achieved = flops / secs / 1e12
+            return {"bound": "alu", "achieved": achieved, "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                     "frac": achieved / FP32_VALU_PEAK_TFLOPS, "traffic": traffic, "kernel": kname,
-                    "flops_per_launch": k1_flops, "bytes_per_launch": k1_bytes,
-                    "hbm_GB_s": k1_bytes / k1_s / 1e9, "hbm_frac": k1_bytes / k1_s / 1e9 / HBM_PEAK_GBS}
-    else:
-        achieved = k1_bytes / k1_s / 1e9
-        roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kname,
-                    "bytes_per_launch": k1_bytes}
+                    "flops_per_launch": flops, "bytes_per_launch": nbytes,
+                    "hbm_GB_s": nbytes / secs / 1e9, "hbm_frac": nbytes / secs / 1e9 / HBM_PEAK_GBS}
+        achieved = nbytes / secs / 1e9
+        return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kname, "bytes_per_launch": nbytes}
+
+    roofline = alu_or_hbm("k2")
+    roofline_k1 = alu_or_hbm("k1")
     # the single-source k1, HBM-bound, for reference
     s_k1 = mdagm["mixed"]["k1_ms"] * 1e-3
     s_bytes = k1_bytes_per_site("mixed", mixed_clover=mc) * Vh
@@ -528,6 +541,7 @@ def main() -> int:
         "copy_GB_s": copy_gbs,
         "force_s": float(np.mean([f["s"] for f in rec["force"]])) if rec["force"] else None,
         "roofline": roofline,
+        "roofline_k1_multi": roofline_k1,
         "roofline_single_source": roofline_single,
         "context": "Cell/B.E. QS20 (the paper): ~10 GFLOPS and ~20 GB/s per kernel; "
                    "8.7x / 9.6x over one 2.33 GHz Xeon core (whole application)",
