@@ -106,8 +106,10 @@ struct qcd_ctx {
   double* fbuf = nullptr;      // su(3) force [V][4][8] for the HMD step
   double* logdet = nullptr;    // ln det A(x) per odd site, from the last clover inversion
 
-  // 64-thread workgroups measured fastest for the stencils at 32^3x64
-  int block() const { return block_opt ? block_opt : 64; }
+  // Measured fastest: 64-thread workgroups for the single-source stencils,
+  // 256 for the multi-source set (a quarter of the partial sums per
+  // right-hand side to finish, and faster FP64 multi-source stencils).
+  int block() const { return block_opt ? block_opt : (w->nr > 1 ? 256 : 64); }
   SpF64 f64(int s) const { return SpF64{w->vec[s], w->gv.stride}; }
   SpRef ref64(int s) const { return SpRef{SP_F64, w->vec[s], nullptr}; }
   SpRef refh(int s) const { return SpRef{SP_H, w->hv[s], w->hs[s]}; }
@@ -173,8 +175,10 @@ int alloc_work(const Geom& g, Work& w, int lg, bool all_slots) {
     }
   }
   A(&w.x32, 6 * S * sizeof(float4));
-  // partial sums: one per workgroup of 64 threads (the smallest block) per right-hand side
-  A(&w.partial, ((size_t)blocks_for(w.gv.Vh, 64) + 64) * w.nr * sizeof(double));
+  // partial sums: one per workgroup of 64 threads (the smallest block) per
+  // right-hand side, then room for their folded span sums
+  const size_t nb64 = blocks_for(w.gv.Vh, 64);
+  A(&w.partial, (nb64 + 64 + nb64 / kFoldSpan + 1) * w.nr * sizeof(double));
   A(&w.st, w.nr * sizeof(CgState));
   if (rc == QCD_OK && hipHostMalloc((void**)&w.st_host, w.nr * sizeof(CgState), hipHostMallocDefault) != hipSuccess)
     rc = fail(QCD_ENOMEM, "pinned host allocation failed");
@@ -367,6 +371,10 @@ int m_parity(qcd_ctx* c, int par, int in_site, int in_nbr, int out, bool dag, in
 }
 
 int nblocks(const qcd_ctx* c) { return blocks_for(c->w->gv.Vh, c->block()); }
+// Folded partial sums go after the partials of the smallest workgroup size.
+double* fold_area(const qcd_ctx* c) {
+  return c->w->partial + ((size_t)blocks_for(c->w->gv.Vh, 64) + 64) * c->w->nr;
+}
 
 int sync_state(qcd_ctx* c) {
   HIPCHK(hipMemcpyAsync(c->w->st_host, c->w->st, c->w->nr * sizeof(CgState), hipMemcpyDeviceToHost, c->stream));
@@ -377,7 +385,7 @@ int sync_state(qcd_ctx* c) {
 // |x|^2 of an FP64 vector into st->scalar and returned (synchronises)
 int norm2_sync(qcd_ctx* c, int s, double* out) {
   HIPCHK(launch_norm2(c->w->gv, c->w->lg, c->ref64(s), c->w->partial, c->block(), c->stream));
-  HIPCHK(launch_fin_scalar(c->w->st, c->w->partial, nblocks(c), c->w->nr, c->stream));
+  HIPCHK(launch_fin_scalar(c->w->st, c->w->partial, nblocks(c), c->w->nr, fold_area(c), c->stream));
   QCHK(sync_state(c));
   *out = c->w->st_host->scalar;
   return QCD_OK;
@@ -386,7 +394,7 @@ int norm2_sync(qcd_ctx* c, int s, double* out) {
 // |x|^2 of each right-hand side of an FP64 vector (synchronises)
 int norm2_each(qcd_ctx* c, int s, double* out) {
   HIPCHK(launch_norm2(c->w->gv, c->w->lg, c->ref64(s), c->w->partial, c->block(), c->stream));
-  HIPCHK(launch_fin_scalar(c->w->st, c->w->partial, nblocks(c), c->w->nr, c->stream));
+  HIPCHK(launch_fin_scalar(c->w->st, c->w->partial, nblocks(c), c->w->nr, fold_area(c), c->stream));
   QCHK(sync_state(c));
   for (int r = 0; r < c->w->nr; ++r) out[r] = c->w->st_host[r].scalar;
   return QCD_OK;
@@ -475,7 +483,7 @@ int residual_f64(qcd_ctx* c, int x, int out_r, const CgState* st) {
 int recompute_residual(qcd_ctx* c, int restart, CgState* posted) {
   QCHK(residual_f64(c, V_X, V_R, nullptr));
   const int slot = next_slot(c);
-  HIPCHK(launch_fin_ru(c->w->st, c->w->partial, nblocks(c), c->w->nr, restart, c->w->mbox_dev, kRing, c->stream));
+  HIPCHK(launch_fin_ru(c->w->st, c->w->partial, nblocks(c), c->w->nr, fold_area(c), restart, c->w->mbox_dev, kRing, c->stream));
   HIPCHK(hipEventRecord(c->ev[slot], c->stream));
   if (posted) QCHK(wait_slot(c, slot, posted));
   return QCD_OK;
@@ -484,7 +492,7 @@ int recompute_residual(qcd_ctx* c, int restart, CgState* posted) {
 int init_recurrence(qcd_ctx* c, double tol, double delta, int max_iter, int mixed, CgState* posted) {
   HIPCHK(launch_norm2(c->w->gv, c->w->lg, c->ref64(V_RHS), c->w->partial, c->block(), c->stream));
   const int slot = next_slot(c);
-  HIPCHK(launch_fin_init(c->w->st, c->w->partial, nblocks(c), c->w->nr, tol, delta, max_iter, mixed, c->w->mbox_dev, kRing, c->stream));
+  HIPCHK(launch_fin_init(c->w->st, c->w->partial, nblocks(c), c->w->nr, fold_area(c), tol, delta, max_iter, mixed, c->w->mbox_dev, kRing, c->stream));
   HIPCHK(hipEventRecord(c->ev[slot], c->stream));
   return wait_slot(c, slot, posted);
 }
@@ -503,23 +511,24 @@ int launch_iter(qcd_ctx* c, bool mixed) {
   // stencil.  (Finishing a reduction inside the stencil that produces it,
   // with a last-workgroup-arrives scheme, needs a device-scope fence per
   // workgroup, which writes back the XCD's L2 on this GPU and made the
-  // iteration three times slower.)
-  const bool fuse = nb <= kFuseFinPartials;
+  // iteration three times slower.)  Workgroup r of the dagger k1 (a grid of
+  // nb workgroups) finishes right-hand side r, so fusing also needs nb >= nr.
+  const bool fuse = nb <= kFuseFinPartials && nb >= c->w->nr;
   if (!mixed) {
     QCHK(k1_f64(c, V_P, V_T, false, c->w->st));
     QCHK(k2_f64(c, V_P, V_T, V_Q, false, 1, 0, 0.0, false, c->w->st));
-    if (!fuse) HIPCHK(launch_fin_alpha(c->w->st, c->w->partial, nb, c->w->nr, c->stream));
+    if (!fuse) HIPCHK(launch_fin_alpha(c->w->st, c->w->partial, nb, c->w->nr, fold_area(c), c->stream));
     QCHK(k1_f64(c, V_Q, V_T, true, c->w->st, fuse));
     QCHK(k2_f64(c, V_Q, V_T, V_R, true, 2, V_R, 0.0, true, c->w->st));
-    HIPCHK(launch_fin_beta(c->w->st, c->w->partial, nb, c->w->nr, c->w->mbox_dev, kRing, c->stream));
+    HIPCHK(launch_fin_beta(c->w->st, c->w->partial, nb, c->w->nr, fold_area(c), c->w->mbox_dev, kRing, c->stream));
     HIPCHK(launch_xp_update_f64(c->w->gv, c->w->lg, c->w->st, c->f64(V_X), c->f64(V_P), c->f64(V_R), c->block(), c->stream));
   } else {
     QCHK(k1_h(c, H_P, H_T, false, c->w->st));
     QCHK(k2_h(c, H_P, H_T, H_Q, false, 1, 0, false, c->w->st));
-    if (!fuse) HIPCHK(launch_fin_alpha(c->w->st, c->w->partial, nb, c->w->nr, c->stream));
+    if (!fuse) HIPCHK(launch_fin_alpha(c->w->st, c->w->partial, nb, c->w->nr, fold_area(c), c->stream));
     QCHK(k1_h(c, H_Q, H_T, true, c->w->st, fuse));
     QCHK(k2_h(c, H_Q, H_T, H_R, true, 2, H_R, true, c->w->st));
-    HIPCHK(launch_fin_beta(c->w->st, c->w->partial, nb, c->w->nr, c->w->mbox_dev, kRing, c->stream));
+    HIPCHK(launch_fin_beta(c->w->st, c->w->partial, nb, c->w->nr, fold_area(c), c->w->mbox_dev, kRing, c->stream));
     HIPCHK(launch_xp_update_h(c->w->gv, c->w->lg, c->w->st, c->f32(), c->h(H_P), c->h(H_R), c->block(), c->stream));
   }
   return QCD_OK;
@@ -1035,11 +1044,11 @@ int solve_packed(qcd_ctx* c, const qcd_solver_params* p, int n, qcd_solver_stats
   // true residual ||b - M x|| / ||b|| on the full lattice, per right-hand side
   double rn[16] = {}, bn[16] = {}, t[16];
   QCHK(m_parity(c, 0, V_X, V_OUT_O, V_AUX, false, 2, V_B_E, -1.0));
-  HIPCHK(launch_fin_scalar(c->w->st, c->w->partial, nb, nr, c->stream));
+  HIPCHK(launch_fin_scalar(c->w->st, c->w->partial, nb, nr, fold_area(c), c->stream));
   QCHK(sync_state(c));
   for (int r = 0; r < nr; ++r) rn[r] += c->w->st_host[r].scalar;
   QCHK(m_parity(c, 1, V_OUT_O, V_X, V_AUX, false, 2, V_B_O, -1.0));
-  HIPCHK(launch_fin_scalar(c->w->st, c->w->partial, nb, nr, c->stream));
+  HIPCHK(launch_fin_scalar(c->w->st, c->w->partial, nb, nr, fold_area(c), c->stream));
   QCHK(sync_state(c));
   for (int r = 0; r < nr; ++r) rn[r] += c->w->st_host[r].scalar;
   QCHK(norm2_each(c, V_B_E, t));
@@ -1118,7 +1127,7 @@ static int force_core(qcd_ctx* c, const qcd_solver_params* p, double* S, CgCount
   CgState s_end = *c->w->st_host;
   // S = Re phi^dag X
   HIPCHK(launch_dot_re(c->w->gv, c->w->lg, c->f64(V_RHS), c->f64(V_X), c->w->partial, c->block(), c->stream));
-  HIPCHK(launch_fin_scalar(c->w->st, c->w->partial, nb, c->w->nr, c->stream));
+  HIPCHK(launch_fin_scalar(c->w->st, c->w->partial, nb, c->w->nr, fold_area(c), c->stream));
   QCHK(sync_state(c));
   if (S) *S = c->w->st_host->scalar;
   *c->w->st_host = s_end;
@@ -1205,7 +1214,7 @@ int qcd_hmd_step(qcd_ctx* c, double dt, void* U_dev, double* P_dev, const void* 
 // beta sum (1 - Re tr P / 3) (synchronises; overwrites the host state mirror)
 static int gauge_action_sync(qcd_ctx* c, double beta, double* S) {
   HIPCHK(launch_plaquette(c->g, c->u18, c->w->partial, c->block(), c->stream));
-  HIPCHK(launch_fin_scalar(c->w->st, c->w->partial, nblocks(c), c->w->nr, c->stream));
+  HIPCHK(launch_fin_scalar(c->w->st, c->w->partial, nblocks(c), c->w->nr, fold_area(c), c->stream));
   QCHK(sync_state(c));
   *S = beta * c->w->st_host->scalar;
   return QCD_OK;
@@ -1214,7 +1223,7 @@ static int gauge_action_sync(qcd_ctx* c, double beta, double* S) {
 // -2 sum_odd ln det A from the last inversion (synchronises)
 static int det_action_sync(qcd_ctx* c, double* S) {
   HIPCHK(launch_sum_cb(c->g, c->logdet, c->w->partial, c->block(), c->stream));
-  HIPCHK(launch_fin_scalar(c->w->st, c->w->partial, nblocks(c), c->w->nr, c->stream));
+  HIPCHK(launch_fin_scalar(c->w->st, c->w->partial, nblocks(c), c->w->nr, fold_area(c), c->stream));
   QCHK(sync_state(c));
   *S = -2.0 * c->w->st_host->scalar;
   return QCD_OK;

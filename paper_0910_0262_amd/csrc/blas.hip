@@ -360,26 +360,43 @@ __global__ void fin_ru_k(CgState* st, const double* partial, int n, int restart,
   post(st, mbox, ring);
 }
 
-#define FIN_LAUNCH(kernel, ...)                                      \
-  hipLaunchKernelGGL(kernel, dim3(nr), dim3(1024), 0, s, __VA_ARGS__); \
+// Span sums of many partials: workgroup (f, r) sums partial[r * n + f * kFoldSpan ...]
+// (at most kFoldSpan of them) in block_sum_partials' fixed order into out[r * nf + f].
+__global__ void __launch_bounds__(256) fold_partials_k(const double* partial, int n, double* out, int nf) {
+  const int f = blockIdx.x, r = blockIdx.y;
+  const int m = min(kFoldSpan, n - f * kFoldSpan);
+  const double s = block_sum_partials(partial + (size_t)r * n + (size_t)f * kFoldSpan, m);
+  if (threadIdx.x == 0) out[(size_t)r * nf + f] = s;
+}
+
+#define FIN_LAUNCH(kernel, ...)                                                                   \
+  if (n >= kFoldMin) {                                                                            \
+    const int nf = blocks_for(n, kFoldSpan);                                                      \
+    hipLaunchKernelGGL(fold_partials_k, dim3(nf, nr), dim3(256), 0, s, partial, n, fold, nf);     \
+    const hipError_t e = hipGetLastError();                                                       \
+    if (e != hipSuccess) return e;                                                                \
+    partial = fold;                                                                               \
+    n = nf;                                                                                       \
+  }                                                                                               \
+  hipLaunchKernelGGL(kernel, dim3(nr), dim3(1024), 0, s, __VA_ARGS__);                             \
   return hipGetLastError();
 
-hipError_t launch_fin_scalar(CgState* st, const double* partial, int n, int nr, hipStream_t s) {
+hipError_t launch_fin_scalar(CgState* st, const double* partial, int n, int nr, double* fold, hipStream_t s) {
   FIN_LAUNCH(fin_scalar_k, st, partial, n)
 }
-hipError_t launch_fin_init(CgState* st, const double* partial, int n, int nr, double tol, double delta, int max_iter,
-                           int mixed, CgState* mbox, int ring, hipStream_t s) {
+hipError_t launch_fin_init(CgState* st, const double* partial, int n, int nr, double* fold, double tol, double delta,
+                           int max_iter, int mixed, CgState* mbox, int ring, hipStream_t s) {
   FIN_LAUNCH(fin_init_k, st, partial, n, tol, delta, max_iter, mixed, mbox, ring)
 }
-hipError_t launch_fin_alpha(CgState* st, const double* partial, int n, int nr, hipStream_t s) {
+hipError_t launch_fin_alpha(CgState* st, const double* partial, int n, int nr, double* fold, hipStream_t s) {
   FIN_LAUNCH(fin_alpha_k, st, partial, n)
 }
-hipError_t launch_fin_beta(CgState* st, const double* partial, int n, int nr, CgState* mbox, int ring,
+hipError_t launch_fin_beta(CgState* st, const double* partial, int n, int nr, double* fold, CgState* mbox, int ring,
                            hipStream_t s) {
   FIN_LAUNCH(fin_beta_k, st, partial, n, mbox, ring)
 }
-hipError_t launch_fin_ru(CgState* st, const double* partial, int n, int nr, int restart, CgState* mbox, int ring,
-                         hipStream_t s) {
+hipError_t launch_fin_ru(CgState* st, const double* partial, int n, int nr, double* fold, int restart, CgState* mbox,
+                         int ring, hipStream_t s) {
   FIN_LAUNCH(fin_ru_k, st, partial, n, restart, mbox, ring)
 }
 

@@ -51,8 +51,9 @@ struct DArgs {
 };
 
 // Workgroups r < fin_nr finish alpha for right-hand side r (the sums of the
-// previous launch's |Mhat p|^2 partials), in the finalisation kernel's own
-// fixed order; whole workgroups take the same branch.
+// previous launch's |Mhat p|^2 partials) with the finalisation kernels' fixed
+// summation, run by this kernel's workgroup size, so the result is the same
+// on every run; whole workgroups take the same branch.
 template <class A>
 __device__ __forceinline__ void fused_fin_alpha(const A& a) {
   if ((int)blockIdx.x >= a.fin_nr) return;

@@ -865,9 +865,19 @@ __device__ __forceinline__ void block_sum_store_seg(double v, double* partial, i
 // every thread.  Deterministic for a given n and blockDim.
 __device__ __forceinline__ double block_sum_partials(const double* p, int n) {
   double s = 0.0;
-  // unrolled so that several loads are in flight; the additions keep their order
-#pragma unroll 8
-  for (int k = threadIdx.x; k < n; k += blockDim.x) s += p[k];
+  // Each thread adds p[t], p[t + B], p[t + 2B], ... in that order (B =
+  // blockDim.x).  Groups of eight are loaded before any of them is added, so
+  // eight loads are in flight rather than one; a load past the end reads the
+  // last partial instead (it is in bounds) and is not added.
+  const int step = blockDim.x;
+  for (int k0 = threadIdx.x; k0 < n; k0 += 8 * step) {
+    double v[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = p[min(k0 + j * step, n - 1)];
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      if (k0 + j * step < n) s += v[j];
+  }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
   __shared__ double red[16];

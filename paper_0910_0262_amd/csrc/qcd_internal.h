@@ -172,14 +172,21 @@ hipError_t launch_unpack_clover(const Geom& g, const double2* clov, double2* use
 hipError_t launch_norm2(const Geom& gv, int lg, SpRef x, double* partial, int block, hipStream_t s);
 hipError_t launch_dot_re(const Geom& gv, int lg, SpF64 a, SpF64 b, double* partial, int block, hipStream_t s);
 // Finalisation kernels: one workgroup per right-hand side (nr of them), each
-// summing its n partials and updating its own state.
-hipError_t launch_fin_scalar(CgState* st, const double* partial, int n, int nr, hipStream_t s);
-hipError_t launch_fin_init(CgState* st, const double* partial, int n, int nr, double tol, double delta, int max_iter,
-                           int mixed, CgState* mbox, int ring, hipStream_t s);
-hipError_t launch_fin_alpha(CgState* st, const double* partial, int n, int nr, hipStream_t s);
-hipError_t launch_fin_beta(CgState* st, const double* partial, int n, int nr, CgState* mbox, int ring, hipStream_t s);
-hipError_t launch_fin_ru(CgState* st, const double* partial, int n, int nr, int restart, CgState* mbox, int ring,
-                         hipStream_t s);
+// summing its n partials and updating its own state.  With kFoldMin or more
+// partials per right-hand side they are first folded, by one workgroup per
+// span of kFoldSpan and right-hand side, into fold[r * nf + f] (nf spans per
+// right-hand side; fold holds nr * nf doubles), which the finalisation kernel
+// then sums: one workgroup alone cannot keep enough loads in flight.
+constexpr int kFoldSpan = 4096;
+constexpr int kFoldMin = 32768;
+hipError_t launch_fin_scalar(CgState* st, const double* partial, int n, int nr, double* fold, hipStream_t s);
+hipError_t launch_fin_init(CgState* st, const double* partial, int n, int nr, double* fold, double tol, double delta,
+                           int max_iter, int mixed, CgState* mbox, int ring, hipStream_t s);
+hipError_t launch_fin_alpha(CgState* st, const double* partial, int n, int nr, double* fold, hipStream_t s);
+hipError_t launch_fin_beta(CgState* st, const double* partial, int n, int nr, double* fold, CgState* mbox, int ring,
+                           hipStream_t s);
+hipError_t launch_fin_ru(CgState* st, const double* partial, int n, int nr, double* fold, int restart, CgState* mbox,
+                         int ring, hipStream_t s);
 hipError_t launch_xp_update_f64(const Geom& gv, int lg, const CgState* st, SpF64 x, SpF64 p, SpF64 r, int block,
                                 hipStream_t s);
 hipError_t launch_xp_update_h(const Geom& gv, int lg, const CgState* st, SpF32 x, SpH p, SpH r, int block,

@@ -92,6 +92,30 @@ def test_multi_with_fp32_clover(case):
         assert rel_err(x[j], refs[j]) < 1e-10, j
 
 
+@pytest.mark.parametrize("block", [64, 128, 256])
+def test_workgroup_sizes(case, block):
+    """Multi-source solves default to 256-thread workgroups and single-source
+    ones to 64; every allowed size gives the oracle's solutions (and, with
+    fewer partial sums per right-hand side, a different but fixed summation
+    order, so each size is deterministic)."""
+    dims, lat, setup, bs, refs = case
+    b = to_dev(bs[:4])
+    lat.set_option(capi.QCD_OPT_BLOCK, block)
+    try:
+        for prec in ("fp64", "mixed"):
+            x, sts = lat.solve_multi(b, prec=prec, tol=1e-12)
+            x2, _ = lat.solve_multi(b, prec=prec, tol=1e-12)
+            assert torch.equal(x, x2), prec
+            for j in range(4):
+                assert sts[j]["converged"] == 1
+                assert rel_err(x[j], refs[j]) < 1e-10, (prec, j)
+            x1, st1 = lat.solve(b[0].contiguous(), prec=prec, tol=1e-12)
+            assert st1["converged"] == 1
+            assert rel_err(x1, refs[0]) < 1e-10, prec
+    finally:
+        lat.set_option(capi.QCD_OPT_BLOCK, 0)
+
+
 def test_links_rederived_after_gauge_reload():
     """A second gauge field loaded into the same context reaches every link
     copy the multi-source kernels read."""
@@ -173,14 +197,18 @@ def test_context_state_after_multi_solve():
     lat.close()
 
 
-def test_full_lattice_eight_sources():
+@pytest.mark.parametrize("block", [0, 64])
+def test_full_lattice_eight_sources(block):
     """32^3 x 64, 8 sources, tol 1e-10, as timed by the benchmark: every solution
     has a relative residual <= 5e-10 under the library's FP64 operator M (the
     stopping test is on the normal equations; single solves land at 1-2e-10),
-    and agrees with the single-source solve to within cond * tol."""
+    and agrees with the single-source solve to within cond * tol.  The default
+    workgroups leave 32768 partial sums per right-hand side, 64-thread ones
+    131072: both are folded in spans before the finalisation kernels."""
     dims, kappa, csw = (32, 32, 32, 64), 0.1255, 1.0
-    print("[multi 32^3x64, 8 sources]", flush=True)
+    print(f"[multi 32^3x64, 8 sources, block {block}]", flush=True)
     lat = Lattice(dims, kappa, csw)
+    lat.set_option(capi.QCD_OPT_BLOCK, block)
     lat.load_gauge(to_dev(synth.random_su3_field(dims, 0.2, 0)))
     b = torch.stack([to_dev(synth.gaussian_source(dims, 0, k)) for k in range(8)])
     for prec in ("mixed", "fp64"):
