@@ -106,9 +106,10 @@ struct qcd_ctx {
   double* fbuf = nullptr;      // su(3) force [V][4][8] for the HMD step
   double* logdet = nullptr;    // ln det A(x) per odd site, from the last clover inversion
 
-  // Measured fastest: 64-thread workgroups for the single-source stencils,
-  // 256 for the multi-source set (a quarter of the partial sums per
-  // right-hand side to finish, and faster FP64 multi-source stencils).
+  // Workgroup size of the stencils and reductions, measured: 64 threads for
+  // single-source work; 256 for the multi-source set, where FP64 solves are
+  // about 1 % faster than at 64 and mixed ones equal (the x/p update keeps
+  // 64 threads, kXpBlock).
   int block() const { return block_opt ? block_opt : (w->nr > 1 ? 256 : 64); }
   SpF64 f64(int s) const { return SpF64{w->vec[s], w->gv.stride}; }
   SpRef ref64(int s) const { return SpRef{SP_F64, w->vec[s], nullptr}; }
