@@ -84,10 +84,11 @@ typedef enum {
                                requires det U = 1; default) or 18 (full matrix)       */
   QCD_OPT_MIXED_CLOVER = 1, /* clover storage in the mixed solver: 16 = binary16 with a
                                per-block FP32 scale (default), 32 = FP32                */
-  QCD_OPT_BLOCK = 2,        /* threads per workgroup of the stencil and vector kernels
-                               (64, 128, 192 or 256); 0 (default) = 64 for single-source
-                               work, 256 for multi-source solves of 2 or more right-
-                               hand sides                                               */
+  QCD_OPT_BLOCK = 2,        /* threads per workgroup of the stencil and reduction
+                               kernels (64, 128, 192 or 256); 0 (default) = 64 for
+                               single-source work, 256 for multi-source solves of 2 or
+                               more right-hand sides.  The CG x/p update always runs
+                               in 64-thread workgroups.                                 */
   QCD_OPT_GRAPH = 3,        /* 1: each CG iteration is replayed as a captured HIP graph;
                                0 (default): its kernels are launched one by one (graph
                                replay measured no faster on MI355X)                     */
