@@ -19,7 +19,8 @@ conventions written out in each function and listed in the design notes:
 Wilson-clover operator in hopping form after Luscher, Sint, Sommer and Weisz
 (Nucl. Phys. B478 (1996) 365), a chiral Euclidean gamma basis, even-odd
 (Schur complement) preconditioning, CG (Hestenes-Stiefel) on the normal
-equations, and the HMD update of the R algorithm at N_f = 2.
+equations, and the HMD update of the R algorithm (the step schedule of
+Gottlieb, Liu, Toussaint, Renken and Sugar, Phys. Rev. D 35 (1987) 2531).
 """
 from .core import (  # noqa: F401
     CloverSetup,
@@ -37,6 +38,6 @@ from .core import (  # noqa: F401
 )
 from .solve import cg, solve_full, dense_matrix  # noqa: F401
 from .force import action, action_and_gradient, project_force, action_variational  # noqa: F401
-from .hmd import expi_su3, hmd_step, hamiltonian  # noqa: F401
+from .hmd import expi_su3, r_step, hmd_step, hamiltonian  # noqa: F401
 from .quant import quantize16, dequantize16, link_to_half12, reconstruct12  # noqa: F401
 from . import md  # noqa: F401

@@ -14,14 +14,15 @@ Textbook definitions, written out:
   S_det = -2 sum_{x odd} ln det A(x)  (A(x) Hermitian positive definite).
 * Force of any part: F^a = dS/dw^a for U -> exp(i w^a T^a) U, obtained from
   the PyTorch-convention gradient G by F^a = Re{ i tr[T^a U G^dag] }.
-* Trajectory: n steps of the position-momentum-position leapfrog of
-  oracle.hmd.  R algorithm for N_f flavours (Gottlieb, Liu, Toussaint,
-  Renken, Sugar, Phys. Rev. D 35 (1987) 2531): in each step the links move
-  by (N_f/2) dt/2, the pseudofermion is refreshed there from the step's own
-  noise vector, the links move on to the midpoint by (1 - N_f/2) dt/2, the
-  momenta take dt times the force with the fermion and determinant parts
-  weighted by N_f/2, and the links take the last dt/2.  At N_f = 2 the
-  refresh happens at the midpoint and the shift vanishes.
+* Trajectory: n steps of the R algorithm for N_f flavours (Gottlieb, Liu,
+  Toussaint, Renken, Sugar, Phys. Rev. D 35 (1987) 2531), with the schedule
+  of oracle.hmd.r_step: in each step the links move by (1 - N_f/2) dt/2, the
+  pseudofermion is refreshed there from the step's own noise vector, the
+  links move on to the midpoint by (N_f/2) dt/2, the momenta take dt times
+  the force with the fermion and determinant parts weighted by N_f/2, and
+  the links take the last dt/2.  At N_f = 2 the refresh happens at the start
+  of the step, which is then a heat-bath of phi and one leapfrog step at
+  fixed phi.
 * Reunitarisation: Gram-Schmidt on rows 0 and 1, row 2 = conj(row0 x row1).
 """
 from __future__ import annotations
@@ -30,7 +31,7 @@ import torch
 
 from .core import CloverSetup, clover_matrix, eo_index
 from .force import action_and_gradient, project_force
-from .hmd import expi_su3
+from .hmd import expi_su3, r_step
 from .solve import _dot, cg
 
 
@@ -104,24 +105,27 @@ def _move(u, p, c):
 
 def trajectory(u0, p0, xis, dt, kappa, csw, beta, with_det=True, n_f=2.0, reunit=False, tol=1e-13,
                t_boundary=-1.0):
-    """len(xis) R-algorithm steps; step k refreshes phi = Mhat^dag xi_k at the shifted time.
+    """len(xis) R-algorithm steps (oracle.hmd.r_step); step k refreshes phi = Mhat^dag xi_k.
 
     Returns (U, P, per-step list of the action parts at each midpoint)."""
-    u = torch.as_tensor(u0)
-    p = torch.as_tensor(p0)
-    wf = n_f / 2.0
     actions = []
-    for xi in xis:
-        u = _move(u, p, wf * dt / 2)
-        phi = CloverSetup(u, kappa, csw, t_boundary).Mhat_dag(torch.as_tensor(xi))
-        u = _move(u, p, (1.0 - wf) * dt / 2)
-        f, parts = total_force(u, phi, kappa, csw, beta, with_det, tol, t_boundary, n_f)
-        p = p - dt * f
-        u = _move(u, p, dt / 2)
-        if reunit:
-            u = reunitarize(u)
+    state = (torch.as_tensor(u0), torch.as_tensor(p0))
+
+    def move(st, h):
+        return _move(st[0], st[1], h), st[1]
+
+    def kick(st, phi, h):
+        f, parts = total_force(st[0], phi, kappa, csw, beta, with_det, tol, t_boundary, n_f)
         actions.append(parts)
-    return u, p, actions
+        return st[0], st[1] - h * f
+
+    for xi in xis:
+        def refresh(st, xi=xi):
+            return CloverSetup(st[0], kappa, csw, t_boundary).Mhat_dag(torch.as_tensor(xi))
+
+        u, p = r_step(state, dt, n_f, move, refresh, kick)
+        state = (reunitarize(u) if reunit else u), p
+    return state[0], state[1], actions
 
 
 def hamiltonian_fixed_phi(u, p, phi_e, kappa, csw, beta, with_det=True, tol=1e-14, t_boundary=-1.0) -> float:

@@ -12,6 +12,10 @@ R-algorithm trajectory and reunitarisation.
   the force of -ln det(M^dag M) of the dense unpreconditioned operator.
 * Leapfrog with phi fixed: energy violation over a fixed trajectory length
   falls as dt^2; exact reversibility.
+* R-algorithm trajectory: at N_f = 2 one step is the Phi algorithm's step
+  (phi drawn at the start, one leapfrog step at fixed phi, with the gauge and
+  determinant forces); the step schedule itself is pinned on a one-variable
+  model in test_oracle_ralg.py.
 * Reunitarisation: output in SU(3); identity on SU(3) input; row 0 direction kept.
 """
 import itertools
@@ -218,6 +222,20 @@ def test_trajectory_two_flavours_matches_single_steps():
         uu, pp = st["U"], st["P"]
     assert float(torch.abs(u - uu).max()) < 1e-13
     assert float(torch.abs(p - pp).max()) < 1e-11
+
+
+@pytest.mark.parametrize("with_det,beta", [(True, BETA), (False, 0.0)])
+def test_trajectory_two_flavours_is_phi_algorithm(with_det, beta):
+    """N_f = 2: phi = Mhat^dag(U_0) xi, then a leapfrog step at fixed phi."""
+    u0 = torch.as_tensor(synth.random_su3_field(DIMS, 0.3, 15))
+    p0 = torch.as_tensor(synth.momenta(DIMS, 15))
+    xi = torch.as_tensor(synth.heatbath_xi(DIMS, 15))
+    dt = 0.03
+    u, p, _ = md.trajectory(u0, p0, [xi], dt, KAPPA, CSW, beta, with_det=with_det, n_f=2.0, tol=1e-14)
+    phi0 = O.CloverSetup(u0, KAPPA, CSW).Mhat_dag(xi)
+    ul, pl = md.leapfrog_fixed_phi(u0, p0, phi0, dt, 1, KAPPA, CSW, beta, with_det=with_det, tol=1e-14)
+    assert float(torch.abs(u - ul).max()) < 1e-13
+    assert float(torch.abs(p - pl).max()) < 1e-13 * max(1.0, float(torch.abs(pl).max()))
 
 
 def test_trajectory_flavour_weight():
