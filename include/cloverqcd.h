@@ -98,6 +98,14 @@ typedef enum {
                                wavefronts per 64 sites (forward and backward hops split,
                                partial sums exchanged in LDS), 0 = one work-item per
                                site as on large lattices                                */
+  QCD_OPT_MIXED_STALL = 5   /* mixed CG fallback threshold, per mille in [1, 999],
+                               default 500: the FP64 |r|^2 recomputed at a reliable
+                               update must fall below value/1000 of the best one so
+                               far; after three reliable updates in a row without such
+                               a fall the mixed recurrence stops and the solve
+                               finishes in FP64 CG from the accumulated solution
+                               (stats.restarts counts it).  Low values force the
+                               fallback, for testing it.                                */
 } qcd_option;
 
 /* Library version, (major << 16) | minor. */
@@ -216,9 +224,12 @@ int qcd_solve_multi(qcd_ctx *ctx, const qcd_solver_params *params, int n_rhs, co
 int qcd_action_force(qcd_ctx *ctx, const qcd_solver_params *params, const void *phi_dev, double *S,
                      void *G_dev, double *F_dev, void *X_dev, qcd_solver_stats *stats);
 
-/* One HMD step of the R algorithm at two flavours (pseudofermion refreshed
- * at the midpoint), fermion action only:
- *   U_1/2 = exp(i dt/2 P) U;  phi = Mhat^dag(U_1/2) xi;
+/* One HMD step of the R algorithm at two flavours, fermion action only.
+ * With two flavours per pseudofermion field the R algorithm (Gottlieb, Liu,
+ * Toussaint, Renken, Sugar, Phys. Rev. D 35 (1987) 2531) draws the noise at
+ * the start of the step, so the step is a heat-bath of phi followed by one
+ * leapfrog step at fixed phi:
+ *   phi = Mhat^dag(U) xi;  U_1/2 = exp(i dt/2 P) U;
  *   P <- P - dt F(U_1/2, phi);  U <- exp(i dt/2 P) U_1/2.
  * U_dev: complex128 [V][4][3][3], in/out (also reloaded into the context).
  * P_dev: float64 [V][4][8] generator coefficients, in/out.
@@ -260,17 +271,20 @@ typedef struct {
 /* One trajectory of the R algorithm for n_f flavours (Gottlieb, Liu,
  * Toussaint, Renken, Sugar, Phys. Rev. D 35 (1987) 2531; the update the
  * paper's application runs, section 1): n_steps leapfrog steps, each
- *   U <- exp(i (n_f/2) dt/2 P) U;     phi = Mhat^dag(U) xi_k;
- *   U <- exp(i (1 - n_f/2) dt/2 P) U;
+ *   U <- exp(i (1 - n_f/2) dt/2 P) U;   phi = Mhat^dag(U) xi_k;
+ *   U <- exp(i (n_f/2) dt/2 P) U;
  *   P <- P - dt [(n_f/2) (F_f(U, phi) + F_det(U)) + F_g(U)];
  *   U <- exp(i dt/2 P) U                (then Gram-Schmidt back to SU(3)
  *                                         if reunitarize: row 0 normalised,
  *                                         row 1 orthogonalised and
  *                                         normalised, row 2 = conj(r0 x r1)),
  * with F_f the force of qcd_action_force, F_det that of
- * qcd_clover_det_action_force and F_g that of qcd_gauge_action_force.  At
- * n_f = 2 phi is refreshed at the step's midpoint; at n_f = 0 the fermion
- * field drops out (params and xi_dev are then not read).
+ * qcd_clover_det_action_force and F_g that of qcd_gauge_action_force.  The
+ * noise is drawn (n_f/2) dt/2 before the force point, which cancels the
+ * O(dt) heating of the noisy force; at n_f = 2 that is the start of the step
+ * (the step of qcd_hmd_step plus the gauge and determinant forces), for
+ * n_f > 2 the links first move back in time; at n_f = 0 the fermion field
+ * drops out (params and xi_dev are then not read).
  * U_dev: complex128 [V][4][3][3], in/out.  P_dev: float64 [V][4][8], in/out.
  * xi_dev: complex128 [n_steps][Vh][4][3] on even sites.  actions (host, may
  * be NULL): float64 [n_steps][3] receives (S_f, S_g, S_det) at each step's

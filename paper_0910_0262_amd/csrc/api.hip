@@ -77,6 +77,7 @@ struct qcd_ctx {
   int use_graph = 0;
   int small_grid = 1;
   int block_opt = 0;
+  int stall_permille = 500;  // mixed CG: a reliable update must take |r|^2 below this fraction of its best
   bool gauge_loaded = false;
   bool clover_ready = false;
 
@@ -659,8 +660,10 @@ int cg_mixed(qcd_ctx* c, const qcd_solver_params* p, CgCounters& cnt) {
     if (s.done) break;
     if (s.ru_count > ru_seen) {
       ru_seen = s.ru_count;
-      // the FP64 residual must keep falling; otherwise finish in FP64 from x_hi
-      if (s.rr_hi < 0.5 * best_rr) {
+      // the FP64 residual must keep falling (|r|^2 below stall_permille / 1000
+      // of its best at some reliable update in every three); otherwise finish
+      // in FP64 from x_hi
+      if (s.rr_hi < 1e-3 * c->stall_permille * best_rr) {
         best_rr = s.rr_hi;
         stall = 0;
       } else if (++stall >= 3) {
@@ -862,6 +865,10 @@ int qcd_set_option(qcd_ctx* c, int option, int value) {
     case QCD_OPT_SMALL_GRID:
       if (value != 0 && value != 1) return fail(QCD_EINVAL, "small-grid option must be 0 or 1");
       c->small_grid = value;
+      return QCD_OK;
+    case QCD_OPT_MIXED_STALL:
+      if (value < 1 || value > 999) return fail(QCD_EINVAL, "mixed stall threshold must lie in [1, 999] per mille");
+      c->stall_permille = value;
       return QCD_OK;
     default:
       return fail(QCD_EINVAL, "unknown option");
@@ -1189,16 +1196,19 @@ int qcd_hmd_step(qcd_ctx* c, double dt, void* U_dev, double* P_dev, const void* 
   const Geom& g = c->g;
   if (!c->fbuf) QCHK(dalloc(&c->fbuf, (size_t)32 * g.V * sizeof(double)));
   if (!c->gint) QCHK(dalloc(&c->gint, (size_t)8 * 9 * g.stride * sizeof(double2)));
-  // U_1/2 = exp(i dt/2 P) U
+  // two flavours per pseudofermion at N_f = 2: the R algorithm draws the
+  // noise at the start of the step, phi = Mhat^dag(U_0) xi
   HIPCHK(launch_pack_gauge(g, (const double2*)U_dev, c->u18, c->stream));
-  HIPCHK(launch_link_exp(g, c->u18, P_dev, 0.5 * dt, c->stream));
   HIPCHK(launch_derive_links(g, c->u18, c->u12, c->uh, c->uh18, c->stream));
   c->gauge_loaded = true;
   QCHK(qcd_build_clover(c));
-  // phi = Mhat^dag xi
   HIPCHK(launch_pack_spinor_cb(g, (const double2*)xi_dev, c->f64(V_IN_E), c->stream));
   QCHK(k1_f64(c, V_IN_E, V_T, true, nullptr));
   QCHK(k2_f64(c, V_IN_E, V_T, V_RHS, true, 0, 0, 0.0, false, nullptr));
+  // U_1/2 = exp(i dt/2 P) U_0, where the force is taken
+  HIPCHK(launch_link_exp(g, c->u18, P_dev, 0.5 * dt, c->stream));
+  HIPCHK(launch_derive_links(g, c->u18, c->u12, c->uh, c->uh18, c->stream));
+  QCHK(qcd_build_clover(c));
   CgCounters cnt;
   int conv = QCD_OK;
   QCHK(force_core(c, p, S, cnt, &conv));
@@ -1305,25 +1315,24 @@ int qcd_md_trajectory(qcd_ctx* c, const qcd_md_params* md, void* U_dev, double* 
   QCHK(ensure_force_buffers(c));
   if (!c->fbuf) QCHK(dalloc(&c->fbuf, (size_t)32 * g.V * sizeof(double)));
   HIPCHK(launch_pack_gauge(g, (const double2*)U_dev, c->u18, c->stream));
-  c->gauge_loaded = true;
-  c->clover_ready = false;
+  QCHK(move_links(c, P_dev, 0.0, false));  // the derived link copies of U_0
   CgCounters cnt;
   int conv_all = QCD_OK;
   for (int k = 0; k < md->n_steps; ++k) {
     double s_f = 0.0, s_g = 0.0, s_d = 0.0;
     if (ferm) {
-      // pseudofermion refresh at U(t + (n_f/2) dt/2), then on to the midpoint
-      QCHK(move_links(c, P_dev, wf * 0.5 * dt, false));
+      // R algorithm (Gottlieb et al. 1987): the noise is drawn (n_f/2) dt/2
+      // before the force point, at U(t + (1 - n_f/2) dt/2); at n_f = 2 that
+      // is the start of the step, and for n_f > 2 the links first move back
+      const double h1 = (1.0 - wf) * 0.5 * dt;
+      if (h1 != 0.0) QCHK(move_links(c, P_dev, h1, false));
       QCHK(qcd_build_clover(c));
       const double2* xi_k = (const double2*)xi_dev + (size_t)k * g.Vh * 12;
       HIPCHK(launch_pack_spinor_cb(g, xi_k, c->f64(V_IN_E), c->stream));
       QCHK(k1_f64(c, V_IN_E, V_T, true, nullptr));
       QCHK(k2_f64(c, V_IN_E, V_T, V_RHS, true, 0, 0, 0.0, false, nullptr));
-      const double h2 = (1.0 - wf) * 0.5 * dt;
-      if (h2 != 0.0) {
-        QCHK(move_links(c, P_dev, h2, false));
-        QCHK(qcd_build_clover(c));
-      }
+      QCHK(move_links(c, P_dev, wf * 0.5 * dt, false));
+      QCHK(qcd_build_clover(c));
     } else {
       QCHK(move_links(c, P_dev, 0.5 * dt, false));
     }

@@ -109,11 +109,35 @@ def test_hmd_step_parity():
     # unitarity is kept by the exponential update
     uu = U.conj().transpose(-1, -2) @ U
     assert torch.abs(uu - torch.eye(3, dtype=torch.complex128, device="cuda")).max() < 1e-13
-    # reversibility: (U1, -P1) with the same xi returns to (U0, -P0)
-    P.neg_()
-    lat.hmd_step(U, P, to_dev(xi), dt, prec="fp64", tol=1e-12)
-    assert torch.abs(U.cpu() - torch.as_tensor(u0)).max() < 1e-11
-    assert torch.abs(P.cpu() + torch.as_tensor(p0)).max() < 1e-9
+    # the same step from the library's own calls in the two-flavour R-algorithm
+    # order: phi = Mhat^dag(U_0) xi, links to the midpoint, force there at fixed phi
+    lat.load_gauge(to_dev(u0))
+    phi0 = lat.apply("Mhatdag", to_dev(xi))
+    Uh = to_dev(u0)
+    lat.md_trajectory(Uh, to_dev(p0), None, 0.5 * dt, 1, beta=0.0, n_f=0.0)
+    lat.load_gauge(Uh)
+    _, _, F, _, _ = lat.action_force(phi0, tol=1e-12, want_X=False)
+    assert max_rel(P, to_dev(p0) - dt * F) < 1e-10
+    lat.close()
+
+
+def test_hmd_step_parity_16x4():
+    """One HMD step at dt = 0.02 on the force workload's lattice (16^4, kappa 0.125, c_sw 1)."""
+    dims, kappa, csw, dt = (16, 16, 16, 16), 0.125, 1.0, 0.02
+    print("[hmd step 16^4: oracle reference]", flush=True)
+    u0 = synth.random_su3_field(dims, 0.3, 4)
+    p0 = synth.momenta(dims, 4)
+    xi = synth.heatbath_xi(dims, 4)
+    ref = O.hmd_step(torch.as_tensor(u0), torch.as_tensor(p0), torch.as_tensor(xi), dt, kappa, csw, tol=1e-13)
+    lat = Lattice(dims, kappa, csw)
+    for prec in ("fp64", "mixed"):
+        U = to_dev(u0)
+        P = to_dev(p0)
+        S, st = lat.hmd_step(U, P, to_dev(xi), dt, prec=prec, tol=1e-12)
+        print(f"  16^4 {prec}: iters={st['iters']} S={S:.12e} oracle {ref['S']:.12e}", flush=True)
+        assert abs(S - ref["S"]) < 1e-10 * abs(ref["S"])
+        assert max_rel(U, ref["U"]) < 1e-9
+        assert max_rel(P, ref["P"]) < 1e-9
     lat.close()
 
 
