@@ -92,7 +92,7 @@ typedef enum {
   QCD_OPT_GRAPH = 3,        /* 1: each CG iteration is replayed as a captured HIP graph;
                                0 (default): its kernels are launched one by one (graph
                                replay measured no faster on MI355X)                     */
-  QCD_OPT_SMALL_GRID = 4    /* single-source stencils on lattices of at most 2^17 sites
+  QCD_OPT_SMALL_GRID = 4,   /* single-source stencils on lattices of at most 2^17 sites
                                (fewer sites per checkerboard than SIMD lanes on the
                                chip), with 64-thread workgroups: 1 (default) = two
                                wavefronts per 64 sites (forward and backward hops split,

@@ -24,6 +24,29 @@ def test_header_declares_the_boundary():
         assert must in names
 
 
+def test_header_is_plain_c():
+    """The boundary header compiles as C99 and as C++17 on its own (no GPU, no HIP types)."""
+    import shutil
+    import subprocess
+
+    for compiler, std in (("gcc", "c99"), ("g++", "c++17")):
+        exe = shutil.which(compiler)
+        if exe is None:
+            pytest.skip(f"{compiler} not found")
+        lang = "c" if compiler == "gcc" else "c++"
+        res = subprocess.run([exe, "-fsyntax-only", "-Wall", "-Werror", f"-std={std}", "-x", lang, HEADER],
+                             capture_output=True, text=True)
+        assert res.returncode == 0, res.stderr
+
+
+def test_options_match_the_header():
+    text = open(HEADER).read()
+    for name in ("QCD_OPT_LINK_RECON", "QCD_OPT_MIXED_CLOVER", "QCD_OPT_BLOCK", "QCD_OPT_GRAPH",
+                 "QCD_OPT_SMALL_GRID", "QCD_OPT_MIXED_STALL"):
+        m = re.search(rf"\b{name}\s*=\s*(\d+)", text)
+        assert m and int(m.group(1)) == getattr(capi, name), name
+
+
 def test_library_exports_every_declared_symbol():
     lib = capi.lib()
     for name in declared_functions():
