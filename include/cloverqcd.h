@@ -98,14 +98,13 @@ typedef enum {
                                wavefronts per 64 sites (forward and backward hops split,
                                partial sums exchanged in LDS), 0 = one work-item per
                                site as on large lattices                                */
-  QCD_OPT_MIXED_STALL = 5   /* mixed CG fallback threshold, per mille in [1, 999],
-                               default 500: the FP64 |r|^2 recomputed at a reliable
-                               update must fall below value/1000 of the best one so
-                               far; after three reliable updates in a row without such
-                               a fall the mixed recurrence stops and the solve
-                               finishes in FP64 CG from the accumulated solution
-                               (stats.restarts counts it).  Low values force the
-                               fallback, for testing it.                                */
+  QCD_OPT_MIXED_STALL = 5   /* mixed CG fallback threshold k in [1, 60], default 1: the
+                               FP64 |r|^2 recomputed at a reliable update must fall
+                               below 2^-k of the best one so far; after three reliable
+                               updates in a row without such a fall the mixed
+                               recurrence stops and the solve finishes in FP64 CG from
+                               the accumulated solution (stats.restarts counts it).
+                               Large k forces the fallback, for testing it.             */
 } qcd_option;
 
 /* Library version, (major << 16) | minor. */

@@ -3,15 +3,23 @@
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
 The paper's run stored its fields in single precision (section 3: the 3x3
-link matrix occupies 72 bytes).  The mixed solver stores spinors and links in
-IEEE binary16; these functions define those encodings in NumPy so that the
-GPU encoders can be compared bit for bit:
+link matrix occupies 72 bytes).  The mixed solver stores spinors, links and
+the clover blocks in IEEE binary16; these functions define those encodings
+in NumPy so that the GPU encoders can be compared bit for bit, and evaluate
+the even-odd operator on the stored values:
 
 * spinor: s = max over the 24 real components of |c| (float32);
   inv = 1 / s in float32 (0 if s == 0); code = binary16(round-to-nearest-even(c * inv))
   with the product formed in float32.  Decoding: float32(code) * s.
 * link: the first two rows (12 reals) of U, each rounded float64 -> float32 ->
   binary16; the third row is rebuilt as conj(row0 x row1), valid for det U = 1.
+* clover: each chiral 6x6 Hermitian block as its 36 reals (6 diagonal, 15
+  upper off-diagonal complex entries), encoded like a spinor with one scale
+  per block (max |real|); the lower triangle is the conjugate of the upper.
+* ``mhat_stored16``: Mhat = A_ee - kappa^2 H_eo A_oo^-1 H_oe evaluated exactly
+  on those stored values -- psi, the links, A_ee, A_oo^-1, the intermediate
+  t = A_oo^-1 H_oe psi and the output each taken through its format -- which
+  is what the mixed stencil computes up to its float32 arithmetic.
 """
 from __future__ import annotations
 
@@ -46,3 +54,75 @@ def reconstruct12(rows01: np.ndarray) -> np.ndarray:
     a, b = rows01[..., 0, :], rows01[..., 1, :]
     c = np.conj(np.cross(a, b))
     return np.stack([a, b, c], -2)
+
+
+def _scaled16(reals: np.ndarray) -> np.ndarray:
+    """Round float reals (..., n) through the scaled binary16 encoding (one float32
+    scale max |real| per leading index) and return the decoded float64 values."""
+    r = reals.astype(np.float32)
+    sc = np.abs(r).max(-1).astype(np.float32)
+    with np.errstate(divide="ignore"):
+        inv = np.where(sc > 0, np.float32(1.0) / np.where(sc > 0, sc, np.float32(1.0)), np.float32(0.0)).astype(np.float32)
+    codes = (r * inv[..., None]).astype(np.float32).astype(np.float16)
+    return (codes.astype(np.float32) * sc[..., None]).astype(np.float64)
+
+
+def roundtrip16(psi):
+    """Spinors (..., 4, 3) complex -> the values their binary16 storage decodes to."""
+    codes, s = quantize16(np.asarray(psi))
+    return dequantize16(codes, s)
+
+
+def link_roundtrip12(u):
+    """U (..., 3, 3) -> the 12-real binary16 link: stored rows decoded, row 2 rebuilt."""
+    u = np.asarray(u)
+    h = link_to_half12(u).astype(np.float64).reshape(u.shape[:-2] + (2, 3, 2))
+    return reconstruct12(h[..., 0] + 1j * h[..., 1])
+
+
+def clover_roundtrip(a12, bits: int = 16):
+    """Block-diagonal clover matrices (..., 12, 12) -> their stored values: per chiral
+    6x6 block binary16 with one scale (bits = 16), or every real in float32 (32)."""
+    a12 = np.asarray(a12)
+    out = np.zeros_like(a12)
+    iu = np.triu_indices(6, 1)
+    for b in range(2):
+        blk = a12[..., 6 * b:6 * b + 6, 6 * b:6 * b + 6]
+        d = np.diagonal(blk, axis1=-2, axis2=-1).real
+        off = blk[..., iu[0], iu[1]]
+        reals = np.concatenate([d, np.stack([off.real, off.imag], -1).reshape(off.shape[:-1] + (30,))], -1)
+        if bits == 16:
+            q = _scaled16(reals)
+        else:
+            q = reals.astype(np.float32).astype(np.float64)
+        qoff = q[..., 6::2] + 1j * q[..., 7::2]
+        nb = np.zeros(blk.shape, dtype=np.complex128)
+        nb[..., np.arange(6), np.arange(6)] = q[..., :6]
+        nb[..., iu[0], iu[1]] = qoff
+        nb[..., iu[1], iu[0]] = np.conj(qoff)
+        out[..., 6 * b:6 * b + 6, 6 * b:6 * b + 6] = nb
+    return out
+
+
+def mhat_stored16(setup, psi_e, dagger: bool = False, clover_bits: int = 16):
+    """Mhat psi_e (Mhat^dag if dagger) evaluated exactly on the mixed solver's stored
+    operands; setup is an oracle.CloverSetup of the FP64 gauge field.  Returns the
+    decoded output (Vh, 4, 3) complex128 and the undecoded value before the output
+    is stored."""
+    import torch
+
+    from .core import from_eo, hop, to_eo
+
+    dims = setup.dims
+    u16 = torch.as_tensor(link_roundtrip12(setup.u.numpy()))
+    a_e = torch.as_tensor(clover_roundtrip(setup.A_e.numpy(), clover_bits))
+    ai_o = torch.as_tensor(clover_roundtrip(setup.Ainv_o.numpy(), clover_bits))
+    psi = torch.as_tensor(roundtrip16(torch.as_tensor(psi_e).numpy()))
+
+    def mv(a, v):
+        return torch.einsum("...ij,...j->...i", a, v.reshape(v.shape[:-2] + (12,))).reshape(v.shape)
+
+    h = to_eo(hop(u16, from_eo(psi, None, dims), setup.tb, dagger), dims)[1]
+    t = torch.as_tensor(roundtrip16(mv(ai_o, h).numpy()))
+    out = mv(a_e, psi) - setup.kappa ** 2 * to_eo(hop(u16, from_eo(None, t, dims), setup.tb, dagger), dims)[0]
+    return torch.as_tensor(roundtrip16(out.numpy())), out

@@ -77,7 +77,7 @@ struct qcd_ctx {
   int use_graph = 0;
   int small_grid = 1;
   int block_opt = 0;
-  int stall_permille = 500;  // mixed CG: a reliable update must take |r|^2 below this fraction of its best
+  int stall_log2 = 1;  // mixed CG: a reliable update must take |r|^2 below 2^-stall_log2 of its best
   bool gauge_loaded = false;
   bool clover_ready = false;
 
@@ -660,10 +660,10 @@ int cg_mixed(qcd_ctx* c, const qcd_solver_params* p, CgCounters& cnt) {
     if (s.done) break;
     if (s.ru_count > ru_seen) {
       ru_seen = s.ru_count;
-      // the FP64 residual must keep falling (|r|^2 below stall_permille / 1000
-      // of its best at some reliable update in every three); otherwise finish
-      // in FP64 from x_hi
-      if (s.rr_hi < 1e-3 * c->stall_permille * best_rr) {
+      // the FP64 residual must keep falling (|r|^2 below 2^-stall_log2 of its
+      // best at one reliable update in every three); otherwise finish in FP64
+      // from x_hi
+      if (s.rr_hi < std::ldexp(best_rr, -c->stall_log2)) {
         best_rr = s.rr_hi;
         stall = 0;
       } else if (++stall >= 3) {
@@ -867,8 +867,8 @@ int qcd_set_option(qcd_ctx* c, int option, int value) {
       c->small_grid = value;
       return QCD_OK;
     case QCD_OPT_MIXED_STALL:
-      if (value < 1 || value > 999) return fail(QCD_EINVAL, "mixed stall threshold must lie in [1, 999] per mille");
-      c->stall_permille = value;
+      if (value < 1 || value > 60) return fail(QCD_EINVAL, "mixed stall exponent must lie in [1, 60]");
+      c->stall_log2 = value;
       return QCD_OK;
     default:
       return fail(QCD_EINVAL, "unknown option");

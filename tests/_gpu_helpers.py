@@ -55,3 +55,97 @@ def make_case(dims, width, kappa, csw, seed=0, t_boundary=-1, field="random"):
 def random_spinor(shape, seed):
     rng = np.random.default_rng(seed)
     return rng.standard_normal(shape + (4, 3)) + 1j * rng.standard_normal(shape + (4, 3))
+
+
+# ---------------------------------------------------------------- binary16 error bound
+U16 = 2.0 ** -11    # binary16 unit roundoff: |round(v) - v| <= U16 |v| for normal v
+U32 = 2.0 ** -24    # binary32 unit roundoff
+SQRT2, SQRT3 = 2.0 ** 0.5, 3.0 ** 0.5
+# max row sum of |entries| of a spin projector 1 -+ gamma_mu, of an SU(3) matrix
+# (unit rows), and a bound on that of the error of a 12-real binary16 link:
+# rows 0, 1 carry at most sqrt(2) U16 per entry (|U_ij| <= 1), the rebuilt row
+# 2 = conj(a x b) at most 2 * 2 * sqrt(2) U16 per entry
+P_NORM, U_NORM, DU_NORM = 2.0, SQRT3, 3 * 4 * SQRT2 * U16
+
+
+def _site_max_real(psi):
+    """Largest |real component| per site: the per-site scale of the binary16 encoding."""
+    return torch.maximum(psi.real.abs(), psi.imag.abs()).amax((-2, -1))
+
+
+def _site_max_abs(psi):
+    return psi.abs().amax((-2, -1))
+
+
+def _nb_sum(f):
+    """Sum of a per-site scalar field (Lt, Lz, Ly, Lx) over the 8 nearest neighbours."""
+    tot = torch.zeros_like(f)
+    for ax in range(4):
+        tot = tot + torch.roll(f, 1, ax) + torch.roll(f, -1, ax)
+    return tot
+
+
+def _clover_norms(a12, bits):
+    """Per site: max row sum of |A| over both chiral 6x6 blocks, and a bound on that
+    of the storage error (binary16 with a per-block scale max |real entry|, or FP32)."""
+    norm, dnorm = [], []
+    for b in range(2):
+        blk = a12[..., 6 * b:6 * b + 6, 6 * b:6 * b + 6]
+        norm.append(blk.abs().sum(-1).amax(-1))
+        if bits == 16:
+            scale = torch.maximum(blk.real.abs(), blk.imag.abs()).amax((-2, -1))
+            dnorm.append(6 * SQRT2 * U16 * scale)
+        else:
+            dnorm.append(U32 * blk.abs().sum(-1).amax(-1))
+    return torch.maximum(*norm), torch.maximum(*dnorm)
+
+
+def mixed_mhat_bound(setup, psi_e, dagger=False, clover_bits=16):
+    """Per even site, a bound on max |component error| of the mixed-precision Mhat
+    (or Mhat^dag) against the exact FP64 value.  Returns (bound, mag, exact):
+    mag bounds the magnitude of the terms summed at the site (the scale of
+    float32 rounding), exact is the FP64 value.
+
+    The mixed path stores psi (binary16, per-site scale), the links (12-real
+    binary16), the clover blocks (binary16 with a per-block scale, or FP32),
+    t = A_oo^-1 H_oe psi (binary16, per-site scale) and the output (binary16,
+    per-site scale), and computes in FP32.  A stored value v with scale s
+    carries at most U16 s per real component (sqrt(2) U16 s per complex one).
+    The errors are carried through k1 and k2 with max-row-sum norms of the
+    spin projectors, links and clover blocks, neighbour by neighbour; FP32
+    arithmetic adds a relative 1e-5 of the terms' magnitudes (far above its
+    rounding, far below the storage error)."""
+    from oracle.core import eo_index
+
+    dims = setup.dims
+    lx, ly, lz, lt = dims
+    grid = (lt, lz, ly, lx)
+    ev, od = eo_index(dims)
+    kap2 = setup.kappa ** 2
+
+    def full(vals_e=None, vals_o=None):
+        f = torch.zeros(setup.V, dtype=torch.float64)
+        if vals_e is not None:
+            f[ev] = vals_e
+        if vals_o is not None:
+            f[od] = vals_o
+        return f.reshape(grid)
+
+    s_psi = _site_max_real(psi_e)
+    d_psi, m_psi = SQRT2 * U16 * s_psi, SQRT2 * s_psi
+    # k1: h = H_oe psi on odd sites, t = A_oo^-1 h stored in binary16
+    d_h = _nb_sum(full(P_NORM * U_NORM * d_psi + P_NORM * DU_NORM * m_psi)).reshape(-1)[od]
+    h = setup.H_oe(psi_e, dagger=dagger)
+    t = setup._mv(setup.Ainv_o, h)
+    n_ai, dn_ai = _clover_norms(setup.Ainv_o, clover_bits)
+    s_t = _site_max_real(t)
+    d_t = n_ai * d_h + dn_ai * _site_max_abs(h) + SQRT2 * U16 * s_t + 1e-5 * n_ai * _site_max_abs(h)
+    m_t = SQRT2 * s_t
+    # k2: out = A_ee psi - kappa^2 H_eo t on even sites, stored in binary16
+    hop_t = _nb_sum(full(None, P_NORM * U_NORM * d_t + P_NORM * DU_NORM * m_t)).reshape(-1)[ev]
+    hop_mag = _nb_sum(full(None, P_NORM * U_NORM * m_t)).reshape(-1)[ev]
+    n_ae, dn_ae = _clover_norms(setup.A_e, clover_bits)
+    out = setup._mv(setup.A_e, psi_e) - kap2 * setup.H_eo(t, dagger=dagger)
+    mag = n_ae * m_psi + kap2 * hop_mag
+    bound = n_ae * d_psi + dn_ae * m_psi + kap2 * hop_t + SQRT2 * U16 * _site_max_real(out) + 1e-5 * mag
+    return bound, mag, out

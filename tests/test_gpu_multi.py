@@ -4,9 +4,10 @@ site, links and clover read once per site for all of them) against the oracle.
 Bar: as for single solves, relative solution error <= 1e-10 per right-hand
 side against the oracle's FP64 solution, both to tol 1e-12, and the oracle's
 operator applied to each GPU solution leaves a relative residual <= 1e-10.
-At 32^3 x 64 (the benchmark's lattice and launch configuration) the oracle
-cannot solve; there each solution is checked through the library's FP64
-operator (itself parity-tested) and against the single-source solve."""
+At 32^3 x 64 (the benchmark's lattice and launch configuration) and 24^3 x 48
+the oracle does not solve (hours per source); there the oracle's operator M is
+applied to GPU solutions (seconds each) and the relative residual must be
+<= 5e-10."""
 import numpy as np
 import pytest
 import torch
@@ -47,6 +48,8 @@ def test_multi_solve_parity(case, prec, n):
     for j in range(n):
         assert sts[j]["converged"] == 1
         assert sts[j]["true_rel_res"] < 1e-10
+        if prec == "mixed":
+            assert sts[j]["reliable_updates"] >= 5
         assert rel_err(x[j], refs[j]) < 1e-10, j
         r = torch.as_tensor(bs[j]) - setup.M(x[j].cpu())
         assert float(torch.linalg.norm(r) / torch.linalg.norm(torch.as_tensor(bs[j]))) < 1e-10
@@ -197,27 +200,52 @@ def test_context_state_after_multi_solve():
     lat.close()
 
 
+@pytest.fixture(scope="module")
+def oracle_32():
+    """The oracle's operator on the benchmark's lattice: 32^3 x 64, kappa 0.1255,
+    c_sw 1, links of width 0.2 from seed 0 (its clover setup takes ~10 s)."""
+    dims, kappa, csw = (32, 32, 32, 64), 0.1255, 1.0
+    print("[oracle setup 32^3x64]", flush=True)
+    u = synth.random_su3_field(dims, 0.2, 0)
+    return u, O.CloverSetup(torch.as_tensor(u), kappa, csw)
+
+
+def _oracle_residual(setup, b, x):
+    """|b - M x| / |b| with the oracle's full-lattice FP64 operator."""
+    bc = b.cpu()
+    return float(torch.linalg.norm(bc - setup.M(x.cpu())) / torch.linalg.norm(bc))
+
+
 @pytest.mark.parametrize("block", [0, 64])
-def test_full_lattice_eight_sources(block):
-    """32^3 x 64, 8 sources, tol 1e-10, as timed by the benchmark: every solution
-    has a relative residual <= 5e-10 under the library's FP64 operator M (the
-    stopping test is on the normal equations; single solves land at 1-2e-10),
-    and agrees with the single-source solve to within cond * tol.  The default
-    workgroups leave 32768 partial sums per right-hand side, 64-thread ones
-    131072: both are folded in spans before the finalisation kernels."""
+def test_full_lattice_eight_sources(block, oracle_32):
+    """32^3 x 64, 8 sources, tol 1e-10, as timed by the benchmark.  The oracle's
+    FP64 operator M applied to sources 0 and 5 of each precision leaves a
+    relative residual <= 5e-10 (the stopping test is on the normal equations;
+    single solves land at 1-2e-10); sources 3 and 7 are checked the same way
+    with the library's FP64 operator, and source 5 agrees with its
+    single-source solve to within cond * tol.  The default workgroups leave
+    32768 partial sums per right-hand side, 64-thread ones 131072: both are
+    folded in spans before the finalisation kernels."""
+    u, setup = oracle_32
     dims, kappa, csw = (32, 32, 32, 64), 0.1255, 1.0
     print(f"[multi 32^3x64, 8 sources, block {block}]", flush=True)
     lat = Lattice(dims, kappa, csw)
     lat.set_option(capi.QCD_OPT_BLOCK, block)
-    lat.load_gauge(to_dev(synth.random_su3_field(dims, 0.2, 0)))
+    lat.load_gauge(to_dev(u))
     b = torch.stack([to_dev(synth.gaussian_source(dims, 0, k)) for k in range(8)])
     for prec in ("mixed", "fp64"):
         x, sts = lat.solve_multi(b, prec=prec, tol=1e-10)
-        print(f"  {prec}: iters={sts[0]['iters']} seconds={sts[0]['seconds']:.3f}", flush=True)
-        for k in (0, 3, 7):
+        print(f"  {prec}: iters={sts[0]['iters']} ru={sts[0]['reliable_updates']} "
+              f"seconds={sts[0]['seconds']:.3f}", flush=True)
+        for k in range(8):
+            assert sts[k]["converged"] == 1
+        for k in (0, 5):
+            res = _oracle_residual(setup, b[k], x[k])
+            print(f"    source {k}: oracle residual {res:.3e}", flush=True)
+            assert res < 5e-10, (prec, k, res)
+        for k in (3, 7):
             r = b[k] - lat.apply("M", x[k].contiguous())
             assert float(torch.linalg.norm(r) / torch.linalg.norm(b[k])) < 5e-10, (prec, k)
-            assert sts[k]["converged"] == 1
         xs, _ = lat.solve(b[5].contiguous(), prec=prec, tol=1e-10)
         assert rel_err(x[5], xs) < 1e-7
         del x
@@ -227,15 +255,18 @@ def test_full_lattice_eight_sources(block):
 def test_ragged_partial_fold():
     """24^3 x 48 with 8 sources and 64-thread workgroups leaves 41472 partial
     sums per right-hand side: ten full spans of 4096 and a last one of 512 are
-    folded before the finalisation kernels.  Every solution meets the
-    residual bar under the library's FP64 operator and matches the solve at
-    the default workgroup size (which does not fold at this size)."""
+    folded before the finalisation kernels.  The oracle's FP64 operator on
+    sources 0 and 4, and the library's on source 7, leave a relative residual
+    <= 5e-10, and each solution matches the solve at the default workgroup
+    size (which does not fold at this size)."""
     dims, kappa, csw = (24, 24, 24, 48), 0.1255, 1.0
     vh = dims[0] * dims[1] * dims[2] * dims[3] // 2
     assert vh * 8 // 64 == 41472 and 41472 % 4096 == 512
-    print("[multi 24^3x48, 8 sources, ragged fold]", flush=True)
+    print("[multi 24^3x48, 8 sources, ragged fold: oracle setup]", flush=True)
+    u = synth.random_su3_field(dims, 0.2, 3)
+    setup = O.CloverSetup(torch.as_tensor(u), kappa, csw)
     lat = Lattice(dims, kappa, csw)
-    lat.load_gauge(to_dev(synth.random_su3_field(dims, 0.2, 3)))
+    lat.load_gauge(to_dev(u))
     b = torch.stack([to_dev(synth.gaussian_source(dims, 3, k)) for k in range(8)])
     try:
         for prec in ("mixed", "fp64"):
@@ -246,8 +277,12 @@ def test_ragged_partial_fold():
             print(f"  {prec}: iters={sts[0]['iters']}", flush=True)
             for k in (0, 4, 7):
                 assert sts[k]["converged"] == 1
-                r = b[k] - lat.apply("M", x[k].contiguous())
-                assert float(torch.linalg.norm(r) / torch.linalg.norm(b[k])) < 5e-10, (prec, k)
+                if k == 7:
+                    r = b[k] - lat.apply("M", x[k].contiguous())
+                    res = float(torch.linalg.norm(r) / torch.linalg.norm(b[k]))
+                else:
+                    res = _oracle_residual(setup, b[k], x[k])
+                assert res < 5e-10, (prec, k, res)
                 assert rel_err(x[k], xd[k]) < 1e-7, (prec, k)
             del x, xd
     finally:

@@ -8,10 +8,10 @@ import pytest
 import torch
 
 import oracle as O
-from oracle.quant import quantize16
-from paper_0910_0262_amd import QCDError, capi, synth
+from oracle.quant import mhat_stored16, quantize16
+from paper_0910_0262_amd import Lattice, QCDError, capi, synth
 
-from ._gpu_helpers import C128, make_case, max_rel, pack_blocks, random_spinor, rel_err, to_dev
+from ._gpu_helpers import C128, make_case, max_rel, mixed_mhat_bound, pack_blocks, random_spinor, rel_err, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -67,17 +67,102 @@ def test_eo_operator_parity(case, op, recon):
 
 @pytest.mark.parametrize("clover_bits", [32, 16])
 def test_mixed_operator_vs_oracle(case, clover_bits):
-    """binary16 storage of spinors (per-site scale) and links, FP32 arithmetic:
-    each stored field carries a relative rounding error of at most 2^-11, so the
-    operator output must agree with the FP64 oracle to a few 1e-3 relative."""
+    """binary16 storage of spinors (per-site scale), links and (by default) the
+    clover blocks, FP32 arithmetic.  Site by site and component by component:
+    * Mhat and Mhat^dag lie within the a-priori bound of the storage errors
+      around the FP64 oracle (mixed_mhat_bound: every stored field off by at
+      most 2^-11 of its scale, carried through both stencil passes);
+    * and within one binary16 rounding of the output (2^-11 of the site's
+      scale) plus float32 arithmetic (5e-5 of the summed terms' magnitude) of
+      the oracle's exact value on the same stored operands (mhat_stored16).
+    Mhat^dag Mhat, two passes of each: relative error <= 5e-3 in norm."""
     dims, lat, setup = case
     lat.set_option(capi.QCD_OPT_MIXED_CLOVER, clover_bits)
     psi = random_spinor((setup.Vh,), 12)
     e = torch.as_tensor(psi)
-    for op, fn in [("Mhat", setup.Mhat), ("MdagM", setup.MdagM)]:
-        got = lat.apply(op, to_dev(psi), prec="mixed")
-        assert rel_err(got, fn(e)) < 5e-3
+    for op, dag in (("Mhat", False), ("Mhatdag", True)):
+        got = lat.apply(op, to_dev(psi), prec="mixed").cpu()
+        bound, mag, exact = mixed_mhat_bound(setup, e, dag, clover_bits)
+        err = torch.abs(got - exact).amax((-2, -1))
+        assert bool((err <= bound).all()), (op, float((err / bound).max()))
+        _, pre = mhat_stored16(setup, e, dag, clover_bits)
+        d = (got - pre)
+        d = torch.maximum(d.real.abs(), d.imag.abs()).amax((-2, -1))
+        tol = 2.0 ** -11 * (1 + 2.0 ** -9) * torch.maximum(pre.real.abs(), pre.imag.abs()).amax((-2, -1)) + 5e-5 * mag
+        print(f"  {op} clover {clover_bits}: max err/bound {float((err / bound).max()):.4f}, "
+              f"max |gpu - stored-operand value| / tol {float((d / tol).max()):.3f}", flush=True)
+        assert bool((d <= tol).all()), (op, float((d / tol).max()))
+    got = lat.apply("MdagM", to_dev(psi), prec="mixed")
+    assert rel_err(got, setup.MdagM(e)) < 5e-3
     lat.set_option(capi.QCD_OPT_MIXED_CLOVER, 16)
+
+
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (10, 6, 4, 6)], ids=["4^4", "10x6x4x6"])
+def test_periodic_time_operator_parity(dims):
+    """t_boundary = +1 (periodic time): no sign on the hops across the time
+    boundary.  FP64 operators to rounding, the mixed Mhat within its bound."""
+    lat, setup, u, ud = make_case(dims, 0.4, 0.124, 1.0, 9, t_boundary=1)
+    lx, ly, lz, lt = dims
+    psi = random_spinor((lt, lz, ly, lx), 20)
+    assert max_rel(lat.apply("M", to_dev(psi)), setup.M(torch.as_tensor(psi))) < 1e-13
+    assert max_rel(lat.apply("Mdag", to_dev(psi)), setup.Mdag(torch.as_tensor(psi))) < 1e-13
+    pe = random_spinor((setup.Vh,), 21)
+    e = torch.as_tensor(pe)
+    for op, fn in (("Mhat", setup.Mhat), ("Mhatdag", setup.Mhat_dag), ("MdagM", setup.MdagM)):
+        assert max_rel(lat.apply(op, to_dev(pe)), fn(e)) < 1e-13, op
+    got = lat.apply("Mhat", to_dev(pe), prec="mixed").cpu()
+    bound, _, exact = mixed_mhat_bound(setup, e, False, 16)
+    assert bool((torch.abs(got - exact).amax((-2, -1)) <= bound).all())
+    # the antiperiodic operator differs: the boundary sign is really applied
+    anti = O.CloverSetup(torch.as_tensor(u), 0.124, 1.0, -1.0)
+    assert max_rel(anti.Mhat(e), setup.Mhat(e)) > 1e-2
+    lat.close()
+
+
+def test_eclover_on_indefinite_odd_block():
+    """A rough field (width 1.0) with c_sw = 5 has odd-site clover blocks with
+    negative eigenvalues (checked here with the oracle's eigvalsh): building the
+    clover fails with QCD_ECLOVER, later applications report QCD_ESTATE, and
+    the same links at c_sw = 4 (every block positive) build and apply."""
+    dims, kappa = (4, 4, 4, 4), 0.125
+    u = synth.random_su3_field(dims, 1.0, 0)
+    ev, od = O.eo_index(dims)
+    a5 = O.clover_matrix(torch.as_tensor(u), kappa, 5.0).reshape(-1, 12, 12)
+    assert float(torch.linalg.eigvalsh(a5[od]).min()) < -0.1
+    a4 = O.clover_matrix(torch.as_tensor(u), kappa, 4.0).reshape(-1, 12, 12)
+    assert float(torch.linalg.eigvalsh(a4).min()) > 0.05
+    lat = Lattice(dims, kappa, 5.0)
+    with pytest.raises(QCDError) as e:
+        lat.load_gauge(to_dev(u))
+    assert e.value.code == capi.QCD_ECLOVER
+    psi = to_dev(random_spinor((128,), 3))
+    with pytest.raises(QCDError) as e:
+        lat.apply("Mhat", psi)
+    assert e.value.code == capi.QCD_ESTATE
+    lat.set_params(kappa, 4.0)
+    lat.build_clover()
+    setup = O.CloverSetup(torch.as_tensor(u), kappa, 4.0)
+    assert max_rel(lat.apply("Mhat", psi), setup.Mhat(psi.cpu())) < 1e-13
+    lat.close()
+
+
+def test_eclover_on_loaded_indefinite_block():
+    """qcd_load_clover with one odd site's first block replaced by minus the
+    identity fails with QCD_ECLOVER; the unmodified blocks load."""
+    dims, kappa, csw = (4, 4, 2, 2), 0.12, 1.0
+    lat, setup, u, ud = make_case(dims, 0.3, kappa, csw, 4)
+    packed = pack_blocks(setup.A.reshape(-1, 12, 12))
+    bad = packed.clone()
+    _, od = O.eo_index(dims)
+    bad[od[5], 0, :6] = -1.0
+    bad[od[5], 0, 6:] = 0.0
+    with pytest.raises(QCDError) as e:
+        lat.load_clover(to_dev(bad))
+    assert e.value.code == capi.QCD_ECLOVER
+    lat.load_clover(to_dev(packed))
+    psi = random_spinor((setup.Vh,), 4)
+    assert max_rel(lat.apply("Mhat", to_dev(psi)), setup.Mhat(torch.as_tensor(psi))) < 1e-13
+    lat.close()
 
 
 @pytest.mark.parametrize("small_grid", [0, 1])

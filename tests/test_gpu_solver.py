@@ -42,6 +42,10 @@ def test_solve_parity(case, prec):
     assert st["converged"] == 1
     assert rel_err(x, ref.x) < 1e-10
     assert st["true_rel_res"] < 1e-10
+    if prec == "mixed":
+        # twelve decades at delta 0.1: the FP64 residual is recomputed many times
+        assert st["reliable_updates"] >= 5
+        assert st["restarts"] == 0
     # the oracle's operator applied to the GPU solution
     r = torch.as_tensor(b) - setup.M(x.cpu())
     assert float(torch.linalg.norm(r) / torch.linalg.norm(torch.as_tensor(b))) < 1e-10
@@ -150,3 +154,26 @@ def test_zero_source():
         x, st = lat.solve(torch.zeros((4, 4, 4, 4, 4, 3), dtype=torch.complex128, device="cuda"), prec=prec)
         assert torch.count_nonzero(x) == 0 and st["iters"] == 0
     lat.close()
+
+
+def test_mixed_fallback_to_fp64(case):
+    """QCD_OPT_MIXED_STALL = 40 asks every reliable update to cut the FP64 |r|^2 to
+    2^-40 of its best; at delta 0.1 each cuts it by about a hundred, so the first
+    three reliable updates (a fall of about 1e-6) count as stalled and the solve
+    finishes in FP64 CG from the accumulated solution: one restart, converged,
+    and the oracle's bar.  The default (k = 1, halving) never falls back here."""
+    dims, lat, setup, b, ref = case
+    lat.set_option(capi.QCD_OPT_MIXED_STALL, 40)
+    try:
+        x, st = lat.solve(to_dev(b), prec="mixed", tol=1e-12)
+    finally:
+        lat.set_option(capi.QCD_OPT_MIXED_STALL, 1)
+    print(f"  fallback: iters={st['iters']} ru={st['reliable_updates']} restarts={st['restarts']}", flush=True)
+    assert st["restarts"] == 1 and st["converged"] == 1
+    assert 3 <= st["reliable_updates"] <= 4
+    assert rel_err(x, ref.x) < 1e-10 and st["true_rel_res"] < 1e-10
+    x2, st2 = lat.solve(to_dev(b), prec="mixed", tol=1e-12)
+    assert st2["restarts"] == 0 and st2["reliable_updates"] > 3
+    for bad in (0, 61):
+        with pytest.raises(QCDError, match="EINVAL"):
+            lat.set_option(capi.QCD_OPT_MIXED_STALL, bad)
