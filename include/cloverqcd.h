@@ -249,6 +249,23 @@ int qcd_hmd_step(qcd_ctx *ctx, double dt, void *U_dev, double *P_dev, const void
  * non-finite beta. */
 int qcd_gauge_action_force(qcd_ctx *ctx, double beta, double *S, void *G_dev, double *F_dev);
 
+/* Allocation-free variant of qcd_gauge_action_force, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the derivative of the Wilson gauge action
+ * on the loaded gauge field, G_dev (complex128 [V][4][3][3]) and F_dev
+ * (float64 [V][4][8]) as in qcd_gauge_action_force, each may be NULL but not
+ * both; the action itself is not computed (it needs a host synchronisation).
+ * It calls no allocator: the force accumulator lives in a fixed 64 MiB
+ * device array of the library, one per GPU, so the lattice is limited to
+ * V <= 116508 sites (QCD_EINVAL beyond, before any device work; 16^4 and
+ * 8x8x16x16 fit, 32^3x64 does not).  Stream-ordered: returns once the two
+ * kernels are enqueued on the context's stream, without waiting.  Every call
+ * on one GPU uses the same array: calls that overlap on one GPU (contexts on
+ * different streams) race; calls on one stream are ordered.  The accumulator
+ * is fully overwritten by each call, so no clearing is needed.  QCD_ESTATE
+ * without a gauge field, QCD_EINVAL for a non-finite beta. */
+int qcd_gauge_force_noalloc(qcd_ctx *ctx, double beta, void *G_dev, double *F_dev);
+
 /* Clover determinant on odd sites, S_det = -2 sum_{x odd} ln det A(x): the
  * factor (det A_oo)^2 of det(M^dag M) = (det A_oo)^2 det(Mhat^dag Mhat) that
  * the even-site pseudofermion does not cover (two flavours).  ln det A comes

@@ -79,6 +79,7 @@ SIGNATURES = {
     "qcd_hmd_step": ([_P, _D, _P, _P, _P, ctypes.POINTER(SolverParams), ctypes.POINTER(_D),
                       ctypes.POINTER(SolverStats)], _I),
     "qcd_gauge_action_force": ([_P, _D, ctypes.POINTER(_D), _P, _P], _I),
+    "qcd_gauge_force_noalloc": ([_P, _D, _P, _P], _I),
     "qcd_clover_det_action_force": ([_P, ctypes.POINTER(_D), _P, _P], _I),
     "qcd_md_trajectory": ([_P, ctypes.POINTER(MDParams), _P, _P, _P, ctypes.POINTER(SolverParams),
                            ctypes.POINTER(_D), ctypes.POINTER(SolverStats)], _I),
@@ -247,6 +248,12 @@ def qcd_gauge_action_force(ctx, beta: float, G: torch.Tensor | None, F: torch.Te
                                        _ptr(G, torch.complex128, volume * 36, "G"),
                                        _ptr(F, torch.float64, volume * 32, "F")))
     return s.value
+
+
+def qcd_gauge_force_noalloc(ctx, beta: float, G: torch.Tensor | None, F: torch.Tensor | None, volume: int) -> None:
+    """Stream-ordered: the caller synchronises before reading G and F."""
+    check(lib().qcd_gauge_force_noalloc(ctx, float(beta), _ptr(G, torch.complex128, volume * 36, "G"),
+                                        _ptr(F, torch.float64, volume * 32, "F")))
 
 
 def qcd_clover_det_action_force(ctx, G: torch.Tensor | None, F: torch.Tensor | None, volume: int) -> float:

@@ -9,10 +9,22 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "cloverqcd.h"
 #include "qcd_internal.h"
+
+// Fixed device scratch of the allocation-free entry point
+// (qcd_gauge_force_noalloc): the gauge-force accumulator [mu][parity][9][Vh]
+// of a lattice of at most kScratchVh checkerboard sites.  Each GPU the
+// library runs on holds its own copy from module load to process end; every
+// call on that GPU shares it.  Host code never passes `scratch` itself to a
+// kernel (that is a host-side stand-in); it uses the per-device address
+// hipGetSymbolAddress returns.
+static constexpr size_t kScratchBytes = (size_t)64 << 20;
+static constexpr size_t kScratchVh = kScratchBytes / (8 * 9 * sizeof(double2));
+static __device__ __align__(256) double2 scratch[kScratchBytes / sizeof(double2)];
 
 using namespace qcd;
 
@@ -238,10 +250,30 @@ void free_ctx(qcd_ctx* c) {
     if (e) (void)hipEventDestroy(e);
 }
 
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double2* g_scratch_dev[kMaxDevices] = {};  // device address of `scratch`, per device
+
 int check_ctx(qcd_ctx* c) {
   if (!c) return fail(QCD_EINVAL, "null context");
   if (hipSetDevice(c->device) != hipSuccess) return fail(QCD_EHIP, "hipSetDevice failed");
   return QCD_OK;
+}
+// Resolve the device address of `scratch` on device `dev` (current), once per device.
+int resolve_scratch(int dev) {
+  if (dev >= kMaxDevices) return fail(QCD_EINVAL, "device index beyond the library's table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_dev[dev]) return QCD_OK;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || p == nullptr)
+    return fail(QCD_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+  g_scratch_dev[dev] = static_cast<double2*>(p);
+  return QCD_OK;
+}
+double2* scratch_of(int dev) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return dev < kMaxDevices ? g_scratch_dev[dev] : nullptr;
 }
 int need_gauge(qcd_ctx* c) {
   if (!c->gauge_loaded) return fail(QCD_ESTATE, "no gauge field loaded");
@@ -769,6 +801,7 @@ int qcd_create(const int dims[4], int device, uintptr_t hip_stream, qcd_ctx** ou
   if (hipGetDeviceCount(&ndev) != hipSuccess || device >= ndev)
     return fail(QCD_EINVAL, "device " + std::to_string(device) + " not available");
   HIPCHK(hipSetDevice(device));
+  QCHK(resolve_scratch(device));
   qcd_ctx* c = new qcd_ctx();
   for (int k = 0; k < 4; ++k) c->dims[k] = dims[k];
   c->device = device;
@@ -1261,6 +1294,24 @@ int qcd_gauge_action_force(qcd_ctx* c, double beta, double* S, void* G_dev, doub
     HIPCHK(launch_force_out(c->g, c->u18, c->gint, (double2*)G_dev, F_dev, c->stream));
   }
   HIPCHK(hipStreamSynchronize(c->stream));
+  return QCD_OK;
+}
+
+int qcd_gauge_force_noalloc(qcd_ctx* c, double beta, void* G_dev, double* F_dev) {
+  QCHK(check_ctx(c));
+  if (!std::isfinite(beta)) return fail(QCD_EINVAL, "beta must be finite");
+  if (!G_dev && !F_dev) return fail(QCD_EINVAL, "G_dev and F_dev are both null");
+  QCHK(need_gauge(c));
+  if ((size_t)c->g.stride > kScratchVh)
+    return fail(QCD_EINVAL, "lattice too large for the allocation-free gauge force: " + std::to_string(c->g.V) +
+                                " sites need " + std::to_string((size_t)8 * 9 * c->g.stride * sizeof(double2)) +
+                                " bytes of scratch, the library holds " + std::to_string(kScratchBytes) +
+                                " (at most " + std::to_string(2 * kScratchVh) + " sites)");
+  double2* acc = scratch_of(c->device);
+  if (!acc) return fail(QCD_ESTATE, "scratch address not resolved on this device");
+  // the accumulator is overwritten (not accumulated) for every link: nothing to clear
+  HIPCHK(launch_gauge_force(c->g, c->u18, -beta / 3.0, 0, acc, c->stream));
+  HIPCHK(launch_force_out(c->g, c->u18, acc, (double2*)G_dev, F_dev, c->stream));
   return QCD_OK;
 }
 
