@@ -8,7 +8,10 @@ and one FP64 multi-source solve (sources interleaved site by site, each link
 and clover block read once per site for all of them), one single-source solve
 of each precision for comparison, one fermion force with the mixed solve
 inside, and a timed run of the stencil kernels (k1, k2, Mhat^dag Mhat) for
-one and for 8 sources.  `value` is the mixed time to solution per source:
+one and for 8 sources.  After the timed region the CPU-baseline leg times the
+oracle (one Mhat^dag Mhat at 32^3 x 64, full solves at 4^4, 8x8x16x16 and
+16^4) and applies the oracle's FP64 operator to every GPU solution of the
+headline solve (relative residual per source and precision).  `value` is the mixed time to solution per source:
 the multi-source solve's time over 8.  All input fields are resident in GPU
 memory before the timed region starts.
 
@@ -167,9 +170,21 @@ def traffic_summary(fetch_csv: str, write_csv: str, vh: int, command: str, nr: i
     print(json.dumps(rec))
 
 
+def host_cpu() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(dims, kappa, csw, u_np, b_np, fp64_iters: int):
     """The oracle as it stands, timed on the host: one Mhat^dag Mhat at the full
-    workload (the sample), scaled by the FP64 CG iteration count of the same solve."""
+    workload (the sample), scaled by the FP64 CG iteration count of the same solve.
+    Returns the record and the oracle's setup (reused for the residual check)."""
     import oracle as O
 
     t0 = time.perf_counter()
@@ -183,11 +198,45 @@ def cpu_baseline(dims, kappa, csw, u_np, b_np, fp64_iters: int):
         "value": t_app * fp64_iters,
         "unit": "s",
         "cores": torch.get_num_threads(),
+        "host_cpu": host_cpu(),
         "kind": "oracle",
         "sample": (f"one oracle Mhat^dag Mhat application at {dims[0]}x{dims[1]}x{dims[2]}x{dims[3]} "
                    f"({t_app:.2f} s, after a {t_setup:.1f} s clover setup) x {fp64_iters} FP64 CG "
                    f"iterations of source 0 = extrapolated oracle CG time-to-solution"),
-    }
+    }, setup
+
+
+def oracle_residuals(setup, b_np, xs_host):
+    """The oracle's FP64 operator on every GPU solution of the headline workload:
+    relative residual |b - M x| / |b| per source and precision."""
+    out = {}
+    for prec, xs in xs_host.items():
+        res = []
+        for k, x in enumerate(xs):
+            b = torch.as_tensor(b_np[k])
+            res.append(float(torch.linalg.norm(b - setup.M(x)) / torch.linalg.norm(b)))
+        out[prec] = res
+        log(f"oracle residuals of the {prec} solutions: max {max(res):.2e}")
+    return out
+
+
+def oracle_small_solves():
+    """Oracle full solves (tol 1e-10) of the two small workloads, timed on the host:
+    4^4 (kappa 0.12, width 0.3) and 8x8x16x16 (kappa 0.124, width 0.5), c_sw 1, seed 0."""
+    import oracle as O
+    from paper_0910_0262_amd import synth
+
+    out = {}
+    for name, dims, width, kappa in (("4^4", (4, 4, 4, 4), 0.3, 0.12), ("8x8x16x16", (8, 8, 16, 16), 0.5, 0.124)):
+        u = synth.random_su3_field(dims, width, 0)
+        b = synth.gaussian_source(dims, 0, 0)
+        t0 = time.perf_counter()
+        ref = O.solve_full(O.CloverSetup(torch.as_tensor(u), kappa, 1.0), torch.as_tensor(b), 1e-10)
+        t = time.perf_counter() - t0
+        out[name] = {"dims": list(dims), "oracle_solve_s": t, "iters": ref.iters, "true_rel_res": ref.true_rel_res,
+                     "cores": torch.get_num_threads()}
+        log(f"oracle solve {name}: {t:.2f} s, {ref.iters} iterations")
+    return out
 
 
 def oracle_check_16(tol_gpu=1e-12):
@@ -550,6 +599,19 @@ def main() -> int:
     if not args.no_trajectory:
         out["trajectory"] = {f"{lx}x{ly}x{lz}x{lt}": trajectory_run(lat, dims, U, 2, 0.02, args.beta, "mixed",
                                                                      args.tol)}
+    # the headline solutions (the solves are bit-reproducible), kept on the host
+    # for the oracle's residual check after the GPU work
+    xs_host = None
+    if not args.no_cpu_baseline:
+        xs_host = {}
+        for prec in ("mixed", "fp64"):
+            if NR > 1:
+                x, _ = lat.solve_multi(B_all, prec=prec, tol=args.tol)
+            else:
+                x1, _ = lat.solve(B[0], prec=prec, tol=args.tol)
+                x = x1.unsqueeze(0)
+            xs_host[prec] = [x[k].cpu() for k in range(NR)]
+            del x
     lat.close()
     del B, B_all, U, XI, phi
     torch.cuda.empty_cache()
@@ -565,11 +627,27 @@ def main() -> int:
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle Mhat^dag Mhat at the full workload")
         fp64_iters = int(round(np.mean(single_of("fp64", "iters"))))
-        out["cpu_baseline"] = cpu_baseline(dims, kappa, csw, u_np, b_np[0], fp64_iters)
+        out["cpu_baseline"], setup = cpu_baseline(dims, kappa, csw, u_np, b_np[0], fp64_iters)
+        if xs_host is not None:
+            res = oracle_residuals(setup, b_np, xs_host)
+            out["oracle_residual_32"] = {"per_source": res,
+                                         "max": {p: max(v) for p, v in res.items()},
+                                         "what": "|b - M x| / |b| with the oracle's FP64 M, every GPU solution "
+                                                 "of the headline solve (tol 1e-10 on the normal equations)"}
+        del setup
         out["oracle_16x4"] = oracle_check_16()
+        out["oracle_small_solves"] = oracle_small_solves()
     else:
         out["cpu_baseline"] = None
         out["oracle_16x4"] = None
+    kids = []
+    try:
+        import psutil
+
+        kids = [f"{c.pid} {' '.join(c.cmdline()[:3])}" for c in psutil.Process().children(recursive=True)]
+    except Exception as e:  # pragma: no cover
+        kids = [f"unknown ({e})"]
+    log(f"child processes at exit: {kids if kids else 'none'}")
     print(json.dumps(out), flush=True)
     return 0
 
