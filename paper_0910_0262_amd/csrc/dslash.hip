@@ -172,8 +172,14 @@ constexpr int stencil_waves() {
 template <typename R, int SITE, bool POST, bool G5IN, bool MULTI, class A>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(stencil_waves<R, SITE, A>())))
 dslash_kernel(A a) {
-  if (a.fin_nr > 0) fused_fin_alpha(a);
-  if (!MULTI && a.st != nullptr && a.st->halt) return;  // uniform over the grid
+  // A launch that finishes alpha itself (fin_nr > 0, the dagger k1) may set
+  // halt while it runs, so it does not read halt at all: it reads no alpha,
+  // and the k2 that consumes its output returns early once halt is set.
+  // Otherwise halt was set by an earlier launch and is uniform over the grid.
+  if (a.fin_nr > 0)
+    fused_fin_alpha(a);
+  else if (!MULTI && a.st != nullptr && a.st->halt)
+    return;
   const int blk = xcd_block(blockIdx.x, gridDim.x);
   const int w = blk * blockDim.x + threadIdx.x;  // work position
   const int r = MULTI ? (w & ((1 << a.lg) - 1)) : 0;
@@ -454,8 +460,12 @@ __device__ __forceinline__ void pair_finish(const A& a, int i, int lane, PairLds
 
 template <typename R, int SITE, bool POST, bool G5IN, class A>
 __global__ void __launch_bounds__(128) dslash_pair_kernel(A a) {
-  if (a.fin_nr > 0) fused_fin_alpha(a);
-  if (a.st != nullptr && a.st->halt) return;  // uniform over the grid
+  // as in dslash_kernel: a launch that finishes alpha never reads halt, so
+  // both wavefronts of every workgroup reach the barriers below
+  if (a.fin_nr > 0)
+    fused_fin_alpha(a);
+  else if (a.st != nullptr && a.st->halt)
+    return;
   __shared__ PairLds<R> L;
   const int blk = xcd_block(blockIdx.x, gridDim.x);
   const int lane = threadIdx.x & 63, h = threadIdx.x >> 6;
