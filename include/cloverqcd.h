@@ -98,13 +98,21 @@ typedef enum {
                                wavefronts per 64 sites (forward and backward hops split,
                                partial sums exchanged in LDS), 0 = one work-item per
                                site as on large lattices                                */
-  QCD_OPT_MIXED_STALL = 5   /* mixed CG fallback threshold k in [1, 60], default 1: the
+  QCD_OPT_MIXED_STALL = 5,  /* mixed CG fallback threshold k in [1, 60], default 1: the
                                FP64 |r|^2 recomputed at a reliable update must fall
                                below 2^-k of the best one so far; after three reliable
                                updates in a row without such a fall the mixed
                                recurrence stops and the solve finishes in FP64 CG from
                                the accumulated solution (stats.restarts counts it).
                                Large k forces the fallback, for testing it.             */
+  QCD_OPT_COMPACT_CLOVER = 6 /* A_ee in the k2 stencils (the site term of the even-odd
+                               operator, FP64 with 12-real links and binary16): 1
+                               (default) = each chiral block as 1 - [[X3, W],
+                               [W^dag, -X3]], X3 traceless Hermitian and W a 3x3
+                               complex matrix (26 reals instead of 36), the form
+                               every clover term built from links has; a loaded
+                               clover term without it uses the general blocks.  0 =
+                               general Hermitian blocks always                          */
 } qcd_option;
 
 /* Library version, (major << 16) | minor. */

@@ -16,6 +16,10 @@ the even-odd operator on the stored values:
 * clover: each chiral 6x6 Hermitian block as its 36 reals (6 diagonal, 15
   upper off-diagonal complex entries), encoded like a spinor with one scale
   per block (max |real|); the lower triangle is the conjugate of the upper.
+* compact clover (A_ee of a clover term built from links): each chiral block
+  is 1 - [[X3, W], [W^dag, -X3]] with X3 traceless Hermitian (3x3 blocks over
+  the two spins of the half); the 26 reals [X3_00, X3_11, X3_01, X3_02, X3_12,
+  W row-major] are encoded like a spinor with one scale per block.
 * ``mhat_stored16``: Mhat = A_ee - kappa^2 H_eo A_oo^-1 H_oe evaluated exactly
   on those stored values -- psi, the links, A_ee, A_oo^-1, the intermediate
   t = A_oo^-1 H_oe psi and the output each taken through its format -- which
@@ -104,9 +108,55 @@ def clover_roundtrip(a12, bits: int = 16):
     return out
 
 
-def mhat_stored16(setup, psi_e, dagger: bool = False, clover_bits: int = 16):
+def compact_blocks(a12):
+    """Block-diagonal clover matrices (..., 12, 12) -> (X3, W) per chiral block,
+    each (..., 2, 3, 3), from B00 = 1 - X3, B11 = 1 + X3, B01 = -W."""
+    a12 = np.asarray(a12)
+    x3, w = [], []
+    for b in range(2):
+        blk = a12[..., 6 * b:6 * b + 6, 6 * b:6 * b + 6]
+        x3.append(0.5 * (blk[..., 3:, 3:] - blk[..., :3, :3]))
+        w.append(-blk[..., :3, 3:])
+    return np.stack(x3, -3), np.stack(w, -3)
+
+
+def blocks_from_compact(x3, w):
+    """Inverse of compact_blocks: the 12x12 block-diagonal matrices."""
+    shp = x3.shape[:-3]
+    out = np.zeros(shp + (12, 12), dtype=np.complex128)
+    eye = np.eye(3)
+    for b in range(2):
+        o = 6 * b
+        out[..., o:o + 3, o:o + 3] = eye - x3[..., b, :, :]
+        out[..., o + 3:o + 6, o + 3:o + 6] = eye + x3[..., b, :, :]
+        out[..., o:o + 3, o + 3:o + 6] = -w[..., b, :, :]
+        out[..., o + 3:o + 6, o:o + 3] = -np.conj(np.swapaxes(w[..., b, :, :], -1, -2))
+    return out
+
+
+def compact_roundtrip16(a12):
+    """A_ee in the compact binary16 form -> the block-diagonal matrices it decodes to
+    (X3's last diagonal entry rebuilt as -(X3_00 + X3_11))."""
+    x3, w = compact_blocks(a12)
+    reals = np.concatenate([x3[..., 0, 0].real[..., None], x3[..., 1, 1].real[..., None],
+                            np.stack([x3[..., 0, 1].real, x3[..., 0, 1].imag, x3[..., 0, 2].real, x3[..., 0, 2].imag,
+                                      x3[..., 1, 2].real, x3[..., 1, 2].imag], -1),
+                            np.stack([w.real, w.imag], -1).reshape(w.shape[:-2] + (18,))], -1)
+    q = _scaled16(reals)
+    d0, d1 = q[..., 0], q[..., 1]
+    x01, x02, x12 = q[..., 2] + 1j * q[..., 3], q[..., 4] + 1j * q[..., 5], q[..., 6] + 1j * q[..., 7]
+    xq = np.zeros(x3.shape, dtype=np.complex128)
+    xq[..., 0, 0], xq[..., 1, 1], xq[..., 2, 2] = d0, d1, -(d0 + d1)
+    xq[..., 0, 1], xq[..., 0, 2], xq[..., 1, 2] = x01, x02, x12
+    xq[..., 1, 0], xq[..., 2, 0], xq[..., 2, 1] = np.conj(x01), np.conj(x02), np.conj(x12)
+    wq = (q[..., 8::2] + 1j * q[..., 9::2]).reshape(w.shape)
+    return blocks_from_compact(xq, wq)
+
+
+def mhat_stored16(setup, psi_e, dagger: bool = False, clover_bits: int = 16, compact: bool = False):
     """Mhat psi_e (Mhat^dag if dagger) evaluated exactly on the mixed solver's stored
-    operands; setup is an oracle.CloverSetup of the FP64 gauge field.  Returns the
+    operands (A_ee in the compact form if compact); setup is an oracle.CloverSetup
+    of the FP64 gauge field.  Returns the
     decoded output (Vh, 4, 3) complex128 and the undecoded value before the output
     is stored."""
     import torch
@@ -115,7 +165,10 @@ def mhat_stored16(setup, psi_e, dagger: bool = False, clover_bits: int = 16):
 
     dims = setup.dims
     u16 = torch.as_tensor(link_roundtrip12(setup.u.numpy()))
-    a_e = torch.as_tensor(clover_roundtrip(setup.A_e.numpy(), clover_bits))
+    if compact and clover_bits == 16:
+        a_e = torch.as_tensor(compact_roundtrip16(setup.A_e.numpy()))
+    else:
+        a_e = torch.as_tensor(clover_roundtrip(setup.A_e.numpy(), clover_bits))
     ai_o = torch.as_tensor(clover_roundtrip(setup.Ainv_o.numpy(), clover_bits))
     psi = torch.as_tensor(roundtrip16(torch.as_tensor(psi_e).numpy()))
 

@@ -105,6 +105,13 @@ struct qcd_ctx {
   float2* clovh_es = nullptr;
   uint4* clovinvh_o = nullptr;
   float2* clovinvh_os = nullptr;
+  // compact A_ee (1 - [[X3, W], [W^dag, -X3]] per chiral block, 26 reals):
+  // valid when the clover term has that form (built from links)
+  double2* clovc_e = nullptr;   // FP64: [26][stride] double2
+  uint4* clovhc_e = nullptr;    // binary16: 6 chunks of uint4 then one of uint2, [stride] each
+  float2* clovhc_es = nullptr;
+  bool compact_ok = false;
+  int compact_clover = 1;       // QCD_OPT_COMPACT_CLOVER
   Work w1;          // single source (operators, solve, force, trajectory)
   Work wm;          // multi-source solves
   Work* w = &w1;    // the set the solver drivers use
@@ -235,6 +242,9 @@ void free_ctx(qcd_ctx* c) {
   f(c->clovh_es);
   f(c->clovinvh_o);
   f(c->clovinvh_os);
+  f(c->clovc_e);
+  f(c->clovhc_e);
+  f(c->clovhc_es);
   free_work(c->w1);
   free_work(c->wm);
   f(c->status);
@@ -254,6 +264,8 @@ constexpr int kMaxDevices = 64;
 std::mutex g_scratch_mu;
 double2* g_scratch_dev[kMaxDevices] = {};  // device address of `scratch`, per device
 
+// the site term of k2 reads the compact A_ee where the clover term has its form
+bool use_compact(const qcd_ctx* c) { return c->compact_clover == 1 && c->compact_ok; }
 int check_ctx(qcd_ctx* c) {
   if (!c) return fail(QCD_EINVAL, "null context");
   if (hipSetDevice(c->device) != hipSuccess) return fail(QCD_EHIP, "hipSetDevice failed");
@@ -331,7 +343,8 @@ int k2_f64(qcd_ctx* c, int site, int t, int out, bool dag, int epi, int y, doubl
   op.site = c->ref64(site);
   op.out = c->ref64(out);
   op.site_mode = 2;
-  op.cpre = ClovRef{CL_F64, c->clov_par(0), nullptr};
+  op.cpre = use_compact(c) && c->link_recon == 12 ? ClovRef{CL_F64C, c->clovc_e, nullptr}
+                                                    : ClovRef{CL_F64, c->clov_par(0), nullptr};
   op.c = -c->kappa * c->kappa;
   op.g5out = dag;
   op.epi = epi;
@@ -344,6 +357,7 @@ int k2_f64(qcd_ctx* c, int site, int t, int out, bool dag, int epi, int y, doubl
 }
 // mixed-precision k1 / k2 on binary16 spinors and links, FP32 arithmetic
 ClovRef mixed_clov(const qcd_ctx* c, bool inverse_odd) {
+  if (c->mixed_clover == 16 && !inverse_odd && use_compact(c)) return ClovRef{CL_HC, c->clovhc_e, c->clovhc_es};
   if (c->mixed_clover == 16)
     return inverse_odd ? ClovRef{CL_H, c->clovinvh_o, c->clovinvh_os} : ClovRef{CL_H, c->clovh_e, c->clovh_es};
   return inverse_odd ? ClovRef{CL_F32, c->clovinv32_o, nullptr} : ClovRef{CL_F32, c->clov32_e, nullptr};
@@ -437,14 +451,17 @@ int norm2_each(qcd_ctx* c, int s, double* out) {
 // algorithmic bytes of one Mhat^dag Mhat per even site (k1 + k2, twice) for
 // nr interleaved right-hand sides: spinors nr times, links and clover once
 double mdagm_bytes_per_site(const qcd_ctx* c, bool mixed, int nr = 1) {
+  // k2's A_ee in the compact form: 26 reals per block instead of 36
   if (!mixed) {
     const double sp = 192.0 * nr, lk = (c->link_recon == 12 ? 96.0 : 144.0), cl = 576.0;
-    const double k1 = sp + 8 * lk + cl + sp, k2 = k1 + sp;
+    const double cl_ee = use_compact(c) && c->link_recon == 12 ? 416.0 : cl;
+    const double k1 = sp + 8 * lk + cl + sp, k2 = sp + 8 * lk + cl_ee + sp + sp;
     return 2.0 * (k1 + k2);
   }
   // links: two binary16 rows for one right-hand side, all nine entries for several
   const double sp = 52.0 * nr, lk = nr > 1 ? 36.0 : 24.0, cl = (c->mixed_clover == 16 ? 152.0 : 288.0);
-  const double k1 = sp + 8 * lk + cl + sp, k2 = k1 + sp;
+  const double cl_ee = c->mixed_clover == 16 && use_compact(c) ? 112.0 : cl;
+  const double k1 = sp + 8 * lk + cl + sp, k2 = sp + 8 * lk + cl_ee + sp + sp;
   return 2.0 * (k1 + k2);
 }
 
@@ -834,9 +851,12 @@ int qcd_create(const int dims[4], int device, uintptr_t hip_stream, qcd_ctx** ou
   A(&c->clovinvh_o, 9 * S * sizeof(uint4));
   A(&c->clovinvh_os, S * sizeof(float2));
   A(&c->logdet, S * sizeof(double));
-  A(&c->status, sizeof(int));
+  A(&c->clovc_e, 26 * S * sizeof(double2));
+  A(&c->clovhc_e, 6 * S * sizeof(uint4) + S * sizeof(uint2));
+  A(&c->clovhc_es, S * sizeof(float2));
+  A(&c->status, 2 * sizeof(int));
   if (rc == QCD_OK) rc = alloc_work(g, c->w1, 0, true);
-  if (rc == QCD_OK && hipHostMalloc((void**)&c->status_host, sizeof(int), hipHostMallocDefault) != hipSuccess)
+  if (rc == QCD_OK && hipHostMalloc((void**)&c->status_host, 2 * sizeof(int), hipHostMallocDefault) != hipSuccess)
     rc = fail(QCD_ENOMEM, "pinned host allocation failed");
   for (int k = 0; k < kRing && rc == QCD_OK; ++k)
     if (hipEventCreateWithFlags(&c->ev[k], hipEventDisableTiming) != hipSuccess) rc = fail(QCD_EHIP, "hipEventCreate failed");
@@ -899,6 +919,10 @@ int qcd_set_option(qcd_ctx* c, int option, int value) {
       if (value != 0 && value != 1) return fail(QCD_EINVAL, "small-grid option must be 0 or 1");
       c->small_grid = value;
       return QCD_OK;
+    case QCD_OPT_COMPACT_CLOVER:
+      if (value != 0 && value != 1) return fail(QCD_EINVAL, "compact clover option must be 0 or 1");
+      c->compact_clover = value;
+      return QCD_OK;
     case QCD_OPT_MIXED_STALL:
       if (value < 1 || value > 60) return fail(QCD_EINVAL, "mixed stall exponent must lie in [1, 60]");
       c->stall_log2 = value;
@@ -927,11 +951,13 @@ int qcd_store_gauge(qcd_ctx* c, void* U_dev) {
 }
 
 static int invert_clover(qcd_ctx* c) {
-  HIPCHK(hipMemsetAsync(c->status, 0, sizeof(int), c->stream));
+  HIPCHK(hipMemsetAsync(c->status, 0, 2 * sizeof(int), c->stream));
   HIPCHK(launch_clover_invert(c->g, c->clov, c->clov_inv, c->clov32_e, c->clovinv32_o, c->clovh_e, c->clovh_es,
                               c->clovinvh_o, c->clovinvh_os, c->logdet, c->status, c->stream));
-  HIPCHK(hipMemcpyAsync(c->status_host, c->status, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(launch_clover_compact(c->g, c->clov, c->clovc_e, c->clovhc_e, c->clovhc_es, c->status + 1, c->stream));
+  HIPCHK(hipMemcpyAsync(c->status_host, c->status, 2 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
+  c->compact_ok = c->status_host[1] == 0;
   if (*c->status_host != 0) {
     c->clover_ready = false;
     return fail(QCD_ECLOVER, "an odd-site clover block is not positive definite");

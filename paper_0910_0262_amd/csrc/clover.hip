@@ -264,6 +264,86 @@ __global__ void __launch_bounds__(64) clover_invert_k(Geom g, const double2* __r
   if (!ok) *status = 1;
 }
 
+// Compact copies of A_ee (the site term of k2): per chiral block X3 and W of
+// 1 - [[X3, W], [W^dag, -X3]] read off the FP64 block, 26 reals, in FP64 and
+// in binary16 with a per-block scale.  The form holds for a clover term built
+// from links; for any other (a loaded one) status is set and the caller keeps
+// the full blocks.
+__global__ void __launch_bounds__(64) clover_compact_k(Geom g, const double2* __restrict__ clov, double2* c64,
+                                                        uint4* ch, float2* chs, int* status) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.Vh) return;
+  const CloverF64 ce{clov, g.stride};
+  float r32[52];
+  float sc[2];
+  double dev = 0.0;
+#pragma unroll 1
+  for (int b = 0; b < 2; ++b) {
+    Block<double> a;
+    load_block(ce, i, b, a);
+    double r[26];
+    r[0] = 0.5 * (a.d[3] - a.d[0]);
+    r[1] = 0.5 * (a.d[4] - a.d[1]);
+    const Cx<double> x01 = 0.5 * (a.o[offd(3, 4)] - a.o[offd(0, 1)]);
+    const Cx<double> x02 = 0.5 * (a.o[offd(3, 5)] - a.o[offd(0, 2)]);
+    const Cx<double> x12 = 0.5 * (a.o[offd(4, 5)] - a.o[offd(1, 2)]);
+    r[2] = x01.re;
+    r[3] = x01.im;
+    r[4] = x02.re;
+    r[5] = x02.im;
+    r[6] = x12.re;
+    r[7] = x12.im;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      const Cx<double> w = a.o[offd(k / 3, 3 + k % 3)];
+      r[8 + 2 * k] = -w.re;
+      r[9 + 2 * k] = -w.im;
+    }
+    // B00 + B11 = 2 and tr X3 = 0
+#pragma unroll
+    for (int k = 0; k < 3; ++k) dev = fmax(dev, fabs(a.d[k] + a.d[3 + k] - 2.0));
+    const Cx<double> s01 = a.o[offd(0, 1)] + a.o[offd(3, 4)], s02 = a.o[offd(0, 2)] + a.o[offd(3, 5)],
+                     s12 = a.o[offd(1, 2)] + a.o[offd(4, 5)];
+    dev = fmax(dev, fmax(fmax(fabs(s01.re), fabs(s01.im)), fmax(fabs(s02.re), fabs(s02.im))));
+    dev = fmax(dev, fmax(fabs(s12.re), fabs(s12.im)));
+    dev = fmax(dev, fabs(a.d[3] + a.d[4] + a.d[5] - a.d[0] - a.d[1] - a.d[2]));
+#pragma unroll
+    for (int k = 0; k < 13; ++k)
+      c64[(size_t)(b * 13 + k) * g.stride + i] = make_double2(r[2 * k], r[2 * k + 1]);
+    float m = 0.f;
+#pragma unroll
+    for (int k = 0; k < 26; ++k) {
+      r32[26 * b + k] = float(r[k]);
+      m = fmaxf(m, fabsf(r32[26 * b + k]));
+    }
+    sc[b] = m;
+  }
+  const float inv0 = sc[0] > 0.f ? 1.0f / sc[0] : 0.f, inv1 = sc[1] > 0.f ? 1.0f / sc[1] : 0.f;
+#pragma unroll
+  for (int k = 0; k < 7; ++k) {
+    h8_t h;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int q = 8 * k + j;
+      h[j] = q < 52 ? (_Float16)(r32[q] * (q < 26 ? inv0 : inv1)) : (_Float16)0.f;
+    }
+    if (k < 6) {
+      ch[(size_t)k * g.stride + i] = from_h8(h);
+    } else {
+      const h4_t t = {h[0], h[1], h[2], h[3]};
+      ((uint2*)(ch + (size_t)6 * g.stride))[i] = from_h4(t);
+    }
+  }
+  chs[i] = make_float2(sc[0], sc[1]);
+  if (dev > 1e-12) *status = 1;
+}
+
+hipError_t launch_clover_compact(const Geom& g, const double2* clov_e, double2* c64, uint4* ch, float2* chs,
+                                 int* status, hipStream_t s) {
+  hipLaunchKernelGGL(clover_compact_k, dim3(blocks_for(g.Vh, 64)), dim3(64), 0, s, g, clov_e, c64, ch, chs, status);
+  return hipGetLastError();
+}
+
 hipError_t launch_clover_invert(const Geom& g, const double2* clov, double2* clov_inv, float4* clov32_e,
                                 float4* clovinv32_o, uint4* clovh_e, float2* clovh_es, uint4* clovinvh_o,
                                 float2* clovinvh_os, double* logdet, int* status, hipStream_t s) {

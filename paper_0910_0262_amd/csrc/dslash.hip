@@ -155,6 +155,16 @@ __device__ __forceinline__ void hop_dir(const A& a, int i, int r, const int x[4]
     accumulate<MU, +1>(acc, uh);
 }
 
+// The site term's clover: general Hermitian blocks, or the compact form of
+// a clover term built from links.
+template <bool FUSED_CL, typename R, class CL>
+__device__ __forceinline__ void site_clover(const CL& c, int i, Spinor<R>& s) {
+  if constexpr (CloverCompact<CL>::value)
+    apply_cclover(c, i, s);
+  else
+    apply_clover<FUSED_CL>(c, i, s);
+}
+
 // MULTI: one work-item per (site, right-hand side) with the right-hand side
 // fastest, so the 1 << lg work-items of a site share its link and clover
 // loads; halted right-hand sides keep computing with alpha = 0 (the grid
@@ -213,7 +223,7 @@ dslash_kernel(A a) {
     Spinor<R> acc;
     if constexpr (SITE_FIRST) {
       load_once(a.site, e, acc);
-      if constexpr (SITE == 2) apply_clover<FUSED_CL>(a.cpre, i, acc);
+      if constexpr (SITE == 2) site_clover<FUSED_CL>(a.cpre, i, acc);
     } else {
       zero(acc);
     }
@@ -235,7 +245,7 @@ dslash_kernel(A a) {
     if constexpr (SITE != 0 && !SITE_FIRST) {
       Spinor<R> sv;
       load_once(a.site, e, sv);
-      if constexpr (SITE == 2) apply_clover<FUSED_CL>(a.cpre, i, sv);
+      if constexpr (SITE == 2) site_clover<FUSED_CL>(a.cpre, i, sv);
 #pragma unroll
       for (int s = 0; s < 4; ++s)
 #pragma unroll
@@ -442,7 +452,20 @@ __device__ __forceinline__ void pair_finish(const A& a, int i, int lane, PairLds
     if constexpr (SITE != 0) {
       Cx<R> sv[6];
       load_half<H>(a.site, i, sv);
-      if constexpr (SITE == 2) apply_block<H, FUSED_CL>(a.cpre, i, sv, R(1));
+      if constexpr (SITE == 2) {
+        if constexpr (CloverCompact<decltype(a.cpre)>::value) {
+          CBlock<R> blk;
+          load_cblock(a.cpre, i, H, blk);
+          R f = R(1);
+          if constexpr (CloverScale<decltype(a.cpre)>::scaled) {
+            const float2 sc = block_scales(a.cpre, i);
+            f = R(H == 0 ? sc.x : sc.y);
+          }
+          cblock_mv(blk, sv, f);
+        } else {
+          apply_block<H, FUSED_CL>(a.cpre, i, sv, R(1));
+        }
+      }
 #pragma unroll
       for (int j = 0; j < 6; ++j) v[j] = v[j] + sv[j];
     }
@@ -523,6 +546,10 @@ template <>
 CloverH cl_of<CloverH>(const ClovRef& r, int stride) { return CloverH{(const uint4*)r.p, r.s, stride}; }
 template <>
 CloverNone cl_of<CloverNone>(const ClovRef&, int) { return CloverNone{}; }
+template <>
+CloverF64C cl_of<CloverF64C>(const ClovRef& r, int stride) { return CloverF64C{(const double2*)r.p, stride}; }
+template <>
+CloverHC cl_of<CloverHC>(const ClovRef& r, int stride) { return CloverHC{(const uint4*)r.p, r.s, stride}; }
 
 template <class T>
 T lk_of(const void* p, int stride);
@@ -603,8 +630,14 @@ static hipError_t run_f64(const Geom& g, const DslashOp& op, int block, hipStrea
   using L = LinkF64<NC>;
   if (op.site_mode == 0 && op.post)
     return run<double, SpF64, SpNone, SpF64, L, CloverNone, CloverF64, 0, true>(g, op, block, s);
-  if (op.site_mode == 2 && !op.post)
+  if (op.site_mode == 2 && !op.post) {
+    if constexpr (NC == 6) {
+      if (op.cpre.kind == CL_F64C)
+        return run<double, SpF64, SpF64, SpF64, L, CloverF64C, CloverNone, 2, false>(g, op, block, s);
+    }
+    if (op.cpre.kind != CL_F64) return hipErrorInvalidValue;
     return run<double, SpF64, SpF64, SpF64, L, CloverF64, CloverNone, 2, false>(g, op, block, s);
+  }
   if (op.site_mode == 1 && !op.post)
     return run<double, SpF64, SpF64, SpF64, L, CloverNone, CloverNone, 1, false>(g, op, block, s);
   if (op.site_mode == 1 && op.post)
@@ -631,11 +664,15 @@ hipError_t launch_dslash(const Geom& g, const DslashOp& op, int block, hipStream
     const int ck = op.post ? op.cpost.kind : op.cpre.kind;
     if (ck == CL_F32) return run_mixed<CloverF32, LinkH12>(g, op, block, s);
     if (ck == CL_H) return run_mixed<CloverH, LinkH12>(g, op, block, s);
+    if (ck == CL_HC && op.site_mode == 2 && !op.post)
+      return run<float, SpH, SpH, SpH, LinkH12, CloverHC, CloverNone, 2, false>(g, op, block, s);
   }
   if (op.in.kind == SP_H && op.link_kind == LK_H18 && op.lg > 0) {
     const int ck = op.post ? op.cpost.kind : op.cpre.kind;
     if (ck == CL_F32) return run_mixed<CloverF32, LinkH18>(g, op, block, s);
     if (ck == CL_H) return run_mixed<CloverH, LinkH18>(g, op, block, s);
+    if (ck == CL_HC && op.site_mode == 2 && !op.post)
+      return run<float, SpH, SpH, SpH, LinkH18, CloverHC, CloverNone, 2, false>(g, op, block, s);
   }
   return hipErrorInvalidValue;
 }

@@ -706,6 +706,146 @@ __device__ __forceinline__ void apply_clover(const CL& c, int i, Spinor<R>& s, R
   }
 }
 
+// ------------------------------------------------------------------ compact clover blocks
+// A chiral block of a clover term built from links has the form
+//   1 - [[X3, W], [W^dag, -X3]]     (3x3 blocks over spin 2b, 2b + 1)
+// because sigma_mu,nu restricted to a chiral half is traceless in spin and
+// F_mu,nu is traceless in colour: X3 is traceless Hermitian and W general.
+// Stored per block: 26 reals [d0, d1, x01, x02, x12, W row-major] with
+// X3 = [[d0, x01, x02], [x01*, d1, x12], [x02*, x12*, -d0 - d1]], against 36
+// for a general Hermitian 6x6 block.
+struct CloverF64C {  // 26 chunks of double2 per site: [block * 13 + k]
+  const double2* p;
+  int stride;
+};
+struct CloverHC {    // 52 binary16 per site (block b: [26 b, 26 b + 26)): 6 chunks
+  const uint4* p;    // of 8 halves, then a chunk of 4 halves at p + 6 stride
+  const float2* s;   // per-block scale, max |real|
+  int stride;
+};
+template <typename R>
+struct CBlock {
+  R d0, d1;
+  Cx<R> x01, x02, x12;
+  Cx<R> w[3][3];
+};
+template <typename R>
+__device__ __forceinline__ void cblock_from_reals(const R r[26], CBlock<R>& b) {
+  b.d0 = r[0];
+  b.d1 = r[1];
+  b.x01 = {r[2], r[3]};
+  b.x02 = {r[4], r[5]};
+  b.x12 = {r[6], r[7]};
+#pragma unroll
+  for (int k = 0; k < 9; ++k) b.w[k / 3][k % 3] = {r[8 + 2 * k], r[9 + 2 * k]};
+}
+template <typename R>
+__device__ __forceinline__ void load_cblock(const CloverF64C& c, int i, int b, CBlock<R>& blk) {
+  R r[26];
+#pragma unroll
+  for (int k = 0; k < 13; ++k) {
+    const double2 d = ld_stream(elem(c.p, (size_t)(b * 13 + k) * c.stride, i));
+    r[2 * k] = R(d.x);
+    r[2 * k + 1] = R(d.y);
+  }
+  cblock_from_reals(r, blk);
+}
+// binary16 entries decoded without the block's scale (applied to the vector)
+template <typename R>
+__device__ __forceinline__ void load_cblock(const CloverHC& c, int i, int b, CBlock<R>& blk) {
+  float r[26];
+#pragma unroll
+  for (int k = 0; k < 7; ++k) {
+    const int lo = 8 * k, n = k < 6 ? 8 : 4;  // half indices [lo, lo + n) of this chunk
+    if (lo + n <= 26 * b || lo >= 26 * b + 26) continue;
+    float h[8];
+    if (k < 6) {
+      const h8_t v = as_h8(ld_stream(elem(c.p, (size_t)k * c.stride, i)));
+#pragma unroll
+      for (int j = 0; j < 8; ++j) h[j] = float(v[j]);
+    } else {
+      const h4_t v = as_h4(ld_stream(elem((const uint2*)(c.p + (size_t)6 * c.stride), 0, i)));
+#pragma unroll
+      for (int j = 0; j < 4; ++j) h[j] = float(v[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int q = lo + j - 26 * b;
+      if (j < n && q >= 0 && q < 26) r[q] = h[j];
+    }
+  }
+  R rr[26];
+#pragma unroll
+  for (int k = 0; k < 26; ++k) rr[k] = R(r[k]);
+  cblock_from_reals(rr, blk);
+}
+template <>
+struct CloverScale<CloverHC> {
+  static constexpr bool scaled = true;
+};
+__device__ __forceinline__ float2 block_scales(const CloverHC& c, int i) { return *elem(c.s, 0, i); }
+
+// v <- v - f [[X3, W], [W^dag, -X3]] v for one 6-vector (spins 2b, 2b + 1)
+template <typename R>
+__device__ __forceinline__ void cblock_mv(const CBlock<R>& a, Cx<R> v[6], R f) {
+  Cx<R> u[3], d[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    u[k] = f * v[k];
+    d[k] = f * v[3 + k];
+  }
+  const R d2 = -(a.d0 + a.d1);
+  // X3 u + W d and X3 d - W^dag u
+  Cx<R> yu[3], yd[3];
+  yu[0] = cfma(a.x02, u[2], cfma(a.x01, u[1], a.d0 * u[0]));
+  yu[1] = cfma(a.x12, u[2], cfmac(a.x01, u[0], a.d1 * u[1]));
+  yu[2] = cfmac(a.x12, u[1], cfmac(a.x02, u[0], d2 * u[2]));
+  yd[0] = cfma(a.x02, d[2], cfma(a.x01, d[1], a.d0 * d[0]));
+  yd[1] = cfma(a.x12, d[2], cfmac(a.x01, d[0], a.d1 * d[1]));
+  yd[2] = cfmac(a.x12, d[1], cfmac(a.x02, d[0], d2 * d[2]));
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      yu[r] = cfma(a.w[r][c], d[c], yu[r]);
+      yd[r] = cfms(conj(a.w[c][r]), u[c], yd[r]);
+    }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    v[k] = v[k] - yu[k];
+    v[3 + k] = v[3 + k] + yd[k];
+  }
+}
+template <class CL>
+struct CloverCompact {
+  static constexpr bool value = false;
+};
+template <>
+struct CloverCompact<CloverF64C> {
+  static constexpr bool value = true;
+};
+template <>
+struct CloverCompact<CloverHC> {
+  static constexpr bool value = true;
+};
+// s <- A s with compact blocks (the site term of k2; no FACT form needed)
+template <typename R, class CL>
+__device__ __forceinline__ void apply_cclover(const CL& c, int i, Spinor<R>& s) {
+  float2 sc = make_float2(1.f, 1.f);
+  if constexpr (CloverScale<CL>::scaled) sc = block_scales(c, i);
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    CBlock<R> blk;
+    load_cblock(c, i, b, blk);
+    Cx<R> v[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) v[k] = s.v[2 * b + k / 3][k % 3];
+    cblock_mv(blk, v, R(b == 0 ? sc.x : sc.y));
+#pragma unroll
+    for (int k = 0; k < 6; ++k) s.v[2 * b + k / 3][k % 3] = v[k];
+  }
+}
+
 // ------------------------------------------------------------------ spin projection
 // Upper two spin components h of (1 + S gamma_mu) psi, S = -1 or +1, in the
 // chiral basis; the lower two are a fixed linear map of h (reconstruct()).

@@ -98,7 +98,7 @@ struct SpRef {
   float* s;  // per-site scale (SP_H)
 };
 enum LinkKind { LK_F64_18 = 0, LK_F64_12 = 1, LK_H12 = 2, LK_H18 = 3 };
-enum ClovKind { CL_NONE = 0, CL_F64 = 1, CL_F32 = 2, CL_H = 3 };
+enum ClovKind { CL_NONE = 0, CL_F64 = 1, CL_F32 = 2, CL_H = 3, CL_F64C = 4, CL_HC = 5 };  // C: compact A_ee
 struct ClovRef {
   int kind;
   const void* p;
@@ -202,6 +202,8 @@ hipError_t launch_stream_copy(const uint4* src, uint4* dst, uint64_t n16, hipStr
 // ---- clover.hip
 hipError_t launch_clover_build(const Geom& g, const double2* u18, double kappa, double csw, double2* clov,
                                hipStream_t s);
+hipError_t launch_clover_compact(const Geom& g, const double2* clov_e, double2* c64, uint4* ch, float2* chs,
+                                 int* status, hipStream_t s);
 hipError_t launch_clover_invert(const Geom& g, const double2* clov, double2* clov_inv, float4* clov32_e,
                                 float4* clovinv32_o, uint4* clovh_e, float2* clovh_es, uint4* clovinvh_o,
                                 float2* clovinvh_os, double* logdet, int* status, hipStream_t s);

@@ -52,21 +52,26 @@ def test_full_operator_parity(case, op):
     assert max_rel(got, ref) < 1e-13
 
 
+@pytest.mark.parametrize("compact", [1, 0])
 @pytest.mark.parametrize("recon", [12, 18])
 @pytest.mark.parametrize("op", ["Mhat", "Mhatdag", "MdagM"])
-def test_eo_operator_parity(case, op, recon):
+def test_eo_operator_parity(case, op, recon, compact):
+    """FP64 even-odd operators; compact: A_ee of the k2 site term in the
+    compact form 1 - [[X3, W], [W^dag, -X3]] (12-real links) or general blocks."""
     dims, lat, setup = case
     lat.set_option(capi.QCD_OPT_LINK_RECON, recon)
+    lat.set_option(capi.QCD_OPT_COMPACT_CLOVER, compact)
     psi = random_spinor((setup.Vh,), 11)
     got = lat.apply(op, to_dev(psi))
     e = torch.as_tensor(psi)
     ref = {"Mhat": setup.Mhat, "Mhatdag": setup.Mhat_dag, "MdagM": setup.MdagM}[op](e)
     lat.set_option(capi.QCD_OPT_LINK_RECON, 12)
+    lat.set_option(capi.QCD_OPT_COMPACT_CLOVER, 1)
     assert max_rel(got, ref) < 1e-13
 
 
-@pytest.mark.parametrize("clover_bits", [32, 16])
-def test_mixed_operator_vs_oracle(case, clover_bits):
+@pytest.mark.parametrize("clover_bits,compact", [(32, 1), (16, 1), (16, 0)])
+def test_mixed_operator_vs_oracle(case, clover_bits, compact):
     """binary16 storage of spinors (per-site scale), links and (by default) the
     clover blocks, FP32 arithmetic.  Site by site and component by component:
     * Mhat and Mhat^dag lie within the a-priori bound of the storage errors
@@ -75,9 +80,11 @@ def test_mixed_operator_vs_oracle(case, clover_bits):
     * and within one binary16 rounding of the output (2^-11 of the site's
       scale) plus float32 arithmetic (5e-5 of the summed terms' magnitude) of
       the oracle's exact value on the same stored operands (mhat_stored16).
-    Mhat^dag Mhat, two passes of each: relative error <= 5e-3 in norm."""
+    Mhat^dag Mhat, two passes of each: relative error <= 5e-3 in norm.
+    compact (binary16 only): A_ee of k2 stored as X3 and W (see the FP64 test)."""
     dims, lat, setup = case
     lat.set_option(capi.QCD_OPT_MIXED_CLOVER, clover_bits)
+    lat.set_option(capi.QCD_OPT_COMPACT_CLOVER, compact)
     psi = random_spinor((setup.Vh,), 12)
     e = torch.as_tensor(psi)
     for op, dag in (("Mhat", False), ("Mhatdag", True)):
@@ -85,7 +92,7 @@ def test_mixed_operator_vs_oracle(case, clover_bits):
         bound, mag, exact = mixed_mhat_bound(setup, e, dag, clover_bits)
         err = torch.abs(got - exact).amax((-2, -1))
         assert bool((err <= bound).all()), (op, float((err / bound).max()))
-        _, pre = mhat_stored16(setup, e, dag, clover_bits)
+        _, pre = mhat_stored16(setup, e, dag, clover_bits, compact=bool(compact))
         d = (got - pre)
         d = torch.maximum(d.real.abs(), d.imag.abs()).amax((-2, -1))
         tol = 2.0 ** -11 * (1 + 2.0 ** -9) * torch.maximum(pre.real.abs(), pre.imag.abs()).amax((-2, -1)) + 5e-5 * mag
@@ -95,6 +102,7 @@ def test_mixed_operator_vs_oracle(case, clover_bits):
     got = lat.apply("MdagM", to_dev(psi), prec="mixed")
     assert rel_err(got, setup.MdagM(e)) < 5e-3
     lat.set_option(capi.QCD_OPT_MIXED_CLOVER, 16)
+    lat.set_option(capi.QCD_OPT_COMPACT_CLOVER, 1)
 
 
 @pytest.mark.parametrize("dims", [(4, 4, 4, 4), (10, 6, 4, 6)], ids=["4^4", "10x6x4x6"])
@@ -208,13 +216,28 @@ def test_gauge_store_roundtrip(case):
 
 
 def test_load_clover_path(case):
-    """qcd_load_clover with the oracle's A gives the oracle's operator."""
+    """qcd_load_clover with the oracle's A gives the oracle's operator.  A loaded
+    clover term whose even blocks lack the compact form (one even site's first
+    diagonal entry raised by 0.05) is used as general blocks: the FP64 and mixed
+    operators still follow the oracle's Mhat with that A."""
     dims, lat, setup = case
     A = pack_blocks(setup.A.reshape(-1, 12, 12)).contiguous().to("cuda")
     lat.load_clover(A)
     psi = random_spinor((setup.Vh,), 14)
+    e = torch.as_tensor(psi)
     got = lat.apply("Mhat", to_dev(psi))
-    assert max_rel(got, setup.Mhat(torch.as_tensor(psi))) < 1e-13
+    assert max_rel(got, setup.Mhat(e)) < 1e-13
+    ev, _ = O.eo_index(dims)
+    a2 = setup.A.reshape(-1, 12, 12).clone()
+    a2[ev[3], 0, 0] += 0.05
+    lat.load_clover(pack_blocks(a2).contiguous().to("cuda"))
+    s2 = O.CloverSetup(torch.as_tensor(setup.u), setup.kappa, setup.csw)
+    s2.A = a2.reshape(setup.A.shape)
+    s2.A_e = a2[ev]
+    ref = s2.Mhat(e)
+    assert max_rel(lat.apply("Mhat", to_dev(psi)), ref) < 1e-13
+    assert rel_err(lat.apply("Mhat", to_dev(psi), prec="mixed"), ref) < 5e-3
+    assert max_rel(ref, setup.Mhat(e)) > 1e-4
     lat.build_clover()
 
 

@@ -116,3 +116,25 @@ def test_mhat_stored16_within_the_rounding_bound(bits):
         assert bool((err <= bound).all())
         rel = float((err / torch.abs(ref).amax((-2, -1))).median())
         assert 2.0 ** -16 < rel < 2.0 ** -9
+
+
+def test_compact_clover_form_of_built_clover():
+    """A clover term built from links has, per chiral block, B00 + B11 = 2, B10 = B01^dag
+    and tr(B11 - B00) = 0 (sigma_mu,nu is traceless on each chiral half and F is
+    traceless), so the compact form (X3, W) holds it exactly; a general Hermitian
+    block does not have the form."""
+    for dims, w, kappa, csw, seed in [((4, 4, 4, 4), 0.5, 0.124, 1.3, 3), ((2, 4, 2, 2), 1.0, 0.13, 2.0, 4)]:
+        u = torch.as_tensor(synth.random_su3_field(dims, w, seed))
+        a = O.clover_matrix(u, kappa, csw).reshape(-1, 12, 12).numpy()
+        x3, wm = Q.compact_blocks(a)
+        assert np.abs(np.trace(x3, axis1=-2, axis2=-1)).max() < 1e-15
+        assert np.abs(x3 - np.conj(np.swapaxes(x3, -1, -2))).max() == 0.0
+        assert np.abs(Q.blocks_from_compact(x3, wm) - a).max() < 1e-15
+        q = Q.compact_roundtrip16(a)
+        assert np.array_equal(q, np.conj(np.swapaxes(q, -1, -2)))
+        # binary16 error relative to the entries X3, W (not to the unit diagonal)
+        scale = max(np.abs(x3).max(), np.abs(wm).max())
+        assert 0 < np.abs(q - a).max() < 2 * scale * 2.0 ** -11
+    g = _herm_blocks(4, 9)
+    x3, wm = Q.compact_blocks(g)
+    assert np.abs(Q.blocks_from_compact(x3, wm) - g).max() > 1e-3
