@@ -605,11 +605,9 @@ def main() -> int:
                    "8.7x / 9.6x over one 2.33 GHz Xeon core (whole application)",
     }
     out["mixed_clover_bits"] = args.mixed_clover
-    if not args.no_trajectory:
-        out["trajectory"] = {f"{lx}x{ly}x{lz}x{lt}": trajectory_run(lat, dims, U, 2, 0.02, args.beta, "mixed",
-                                                                     args.tol)}
     # the headline solutions (the solves are bit-reproducible), kept on the host
-    # for the oracle's residual check after the GPU work
+    # for the oracle's residual check after the GPU work; before the trajectory,
+    # which leaves its evolved links in the context
     xs_host = None
     if not args.no_cpu_baseline:
         xs_host = {}
@@ -621,6 +619,9 @@ def main() -> int:
                 x = x1.unsqueeze(0)
             xs_host[prec] = [x[k].cpu() for k in range(NR)]
             del x
+    if not args.no_trajectory:
+        out["trajectory"] = {f"{lx}x{ly}x{lz}x{lt}": trajectory_run(lat, dims, U, 2, 0.02, args.beta, "mixed",
+                                                                     args.tol)}
     lat.close()
     del B, B_all, U, XI, phi
     torch.cuda.empty_cache()
