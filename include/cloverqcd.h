@@ -105,7 +105,7 @@ typedef enum {
                                recurrence stops and the solve finishes in FP64 CG from
                                the accumulated solution (stats.restarts counts it).
                                Large k forces the fallback, for testing it.             */
-  QCD_OPT_COMPACT_CLOVER = 6 /* A_ee in the k2 stencils (the site term of the even-odd
+  QCD_OPT_COMPACT_CLOVER = 6, /* A_ee in the k2 stencils (the site term of the even-odd
                                operator, FP64 with 12-real links and binary16): 1
                                (default) = each chiral block as 1 - [[X3, W],
                                [W^dag, -X3]], X3 traceless Hermitian and W a 3x3
@@ -113,6 +113,14 @@ typedef enum {
                                every clover term built from links has; a loaded
                                clover term without it uses the general blocks.  0 =
                                general Hermitian blocks always                          */
+  QCD_OPT_X_CYCLE = 7       /* CG iterations per update of the solution, n in [1, 4],
+                               default 4: the search directions of n iterations are
+                               kept (n buffers) and x += alpha_0 p_0 + ... +
+                               alpha_{n-1} p_{n-1} is done once per n iterations, which
+                               saves reading and writing x in the other n - 1; a
+                               recurrence that stops or a reliable update inside a
+                               cycle takes the directions it has so far.  The same
+                               CG iterates up to rounding for every n.                  */
 } qcd_option;
 
 /* Library version, (major << 16) | minor. */

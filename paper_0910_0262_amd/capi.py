@@ -24,7 +24,7 @@ STATUS_NAMES = {0: "QCD_OK", -1: "QCD_EINVAL", -2: "QCD_ESTATE", -3: "QCD_ENOMEM
 QCD_FP64, QCD_MIXED = 0, 1
 QCD_OP_M, QCD_OP_MDAG, QCD_OP_MHAT, QCD_OP_MHATDAG, QCD_OP_MHATDAGMHAT = 0, 1, 2, 3, 4
 QCD_OPT_LINK_RECON, QCD_OPT_MIXED_CLOVER, QCD_OPT_BLOCK, QCD_OPT_GRAPH, QCD_OPT_SMALL_GRID = 0, 1, 2, 3, 4
-QCD_OPT_MIXED_STALL, QCD_OPT_COMPACT_CLOVER = 5, 6
+QCD_OPT_MIXED_STALL, QCD_OPT_COMPACT_CLOVER, QCD_OPT_X_CYCLE = 5, 6, 7
 
 
 class QCDError(RuntimeError):

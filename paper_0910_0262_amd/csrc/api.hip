@@ -50,9 +50,11 @@ int fail(int code, const std::string& msg) {
   } while (0)
 
 // FP64 work vectors (one checkerboard each)
-enum Slot { V_IN_E, V_IN_O, V_OUT_E, V_OUT_O, V_T, V_Q, V_X, V_R, V_P, V_RHS, V_B_E, V_B_O, V_AUX, V_Y, V_W, V_Z, NSLOT };
+// (V_P, V_P1, V_P2, V_P3 and H_P .. H_P3: the search directions of one x cycle, see the CG vector updates)
+enum Slot { V_IN_E, V_IN_O, V_OUT_E, V_OUT_O, V_T, V_Q, V_X, V_R, V_P, V_RHS, V_B_E, V_B_O, V_AUX, V_Y, V_W, V_Z,
+            V_P1, V_P2, V_P3, NSLOT };
 // binary16 work vectors
-enum HSlot { H_P, H_T, H_Q, H_R, H_IN, H_OUT, NHSLOT };
+enum HSlot { H_P, H_T, H_Q, H_R, H_IN, H_OUT, H_P1, H_P2, H_P3, NHSLOT };
 // ring of mailbox slots / events for the iterations in flight
 constexpr int kRing = 64;
 
@@ -90,6 +92,7 @@ struct qcd_ctx {
   int small_grid = 1;
   int block_opt = 0;
   int stall_log2 = 1;  // mixed CG: a reliable update must take |r|^2 below 2^-stall_log2 of its best
+  int x_defer = 4;     // CG: iterations per x update (QCD_OPT_X_CYCLE)
   bool gauge_loaded = false;
   bool clover_ready = false;
 
@@ -118,7 +121,7 @@ struct qcd_ctx {
   int wm_lg_alloc = -1;  // right-hand sides (log2) wm was allocated for
   hipEvent_t ev[kRing] = {};
   hipStream_t cap = nullptr;    // private stream used only to capture graphs
-  hipGraphExec_t iter_graph[2] = {nullptr, nullptr};  // one CG iteration: [FP64, mixed]
+  hipGraphExec_t iter_graph[2][4] = {};  // one CG iteration: [FP64, mixed][position in the x cycle]
   int* status = nullptr;
   int* status_host = nullptr;  // pinned
   double2* xi = nullptr;       // clover-force Xi: [par][6][9][stride]
@@ -135,6 +138,9 @@ struct qcd_ctx {
   SpRef ref64(int s) const { return SpRef{SP_F64, w->vec[s], nullptr}; }
   SpRef refh(int s) const { return SpRef{SP_H, w->hv[s], w->hs[s]}; }
   SpH h(int s) const { return SpH{w->hv[s], w->hs[s], w->gv.stride}; }
+  // slot of the j-th search direction of the x cycle
+  static int pslot(int j) { return j == 0 ? V_P : V_P1 + j - 1; }
+  static int hpslot(int j) { return j == 0 ? H_P : H_P1 + j - 1; }
   SpF32 f32() const { return SpF32{w->x32, w->gv.stride}; }
   const void* links64() const { return link_recon == 12 ? (const void*)u12 : (const void*)u18; }
   int lk64() const { return link_recon == 12 ? LK_F64_12 : LK_F64_18; }
@@ -180,8 +186,8 @@ int alloc_work(const Geom& g, Work& w, int lg, bool all_slots) {
   auto A = [&](auto** p, size_t bytes) {
     if (rc == QCD_OK) rc = dalloc(p, bytes);
   };
-  static const int solver_slots[] = {V_T, V_Q, V_X, V_R, V_P, V_RHS, V_B_E, V_B_O, V_AUX, V_OUT_O};
-  static const int solver_hslots[] = {H_P, H_T, H_Q, H_R};
+  static const int solver_slots[] = {V_T, V_Q, V_X, V_R, V_P, V_RHS, V_B_E, V_B_O, V_AUX, V_OUT_O, V_P1, V_P2, V_P3};
+  static const int solver_hslots[] = {H_P, H_T, H_Q, H_R, H_P1, H_P2, H_P3};
   if (all_slots) {
     for (int k = 0; k < NSLOT; ++k) A(&w.vec[k], 12 * S * sizeof(double2));
     for (int k = 0; k < NHSLOT; ++k) {
@@ -253,8 +259,9 @@ void free_ctx(qcd_ctx* c) {
   f(c->fbuf);
   f(c->logdet);
   if (c->status_host) (void)hipHostFree(c->status_host);
-  for (auto& gx : c->iter_graph)
-    if (gx) (void)hipGraphExecDestroy(gx);
+  for (auto& row : c->iter_graph)
+    for (auto& gx : row)
+      if (gx) (void)hipGraphExecDestroy(gx);
   if (c->cap) (void)hipStreamDestroy(c->cap);
   for (auto& e : c->ev)
     if (e) (void)hipEventDestroy(e);
@@ -531,10 +538,12 @@ int residual_f64(qcd_ctx* c, int x, int out_r, const CgState* st) {
 }
 
 // r = rhs - A x in FP64, posted as a reliable update (restart = 0) or a restart
-int recompute_residual(qcd_ctx* c, int restart, CgState* posted) {
+// (nclear: the newest alphas whose directions the caller already took into x)
+int recompute_residual(qcd_ctx* c, int restart, CgState* posted, int nclear = 0) {
   QCHK(residual_f64(c, V_X, V_R, nullptr));
   const int slot = next_slot(c);
-  HIPCHK(launch_fin_ru(c->w->st, c->w->partial, nblocks(c), c->w->nr, fold_area(c), restart, c->w->mbox_dev, kRing, c->stream));
+  HIPCHK(launch_fin_ru(c->w->st, c->w->partial, nblocks(c), c->w->nr, fold_area(c), restart, nclear, c->w->mbox_dev,
+                       kRing, c->stream));
   HIPCHK(hipEventRecord(c->ev[slot], c->stream));
   if (posted) QCHK(wait_slot(c, slot, posted));
   return QCD_OK;
@@ -554,9 +563,11 @@ constexpr int kFuseFinPartials = 1024;
 // streamed faster than 256 for several right-hand sides.
 constexpr int kXpBlock = 64;
 
-// The kernels of one CG iteration (they read alpha, beta and the halt flag
-// from the device state, so the sequence is the same every iteration).
-int launch_iter(qcd_ctx* c, bool mixed) {
+// The kernels of one CG iteration, the j-th of an x cycle of c->x_defer (they
+// read alpha, beta and the halt flag from the device state, so the sequence
+// is the same every cycle).
+int launch_iter(qcd_ctx* c, bool mixed, int j) {
+  const int n = c->x_defer;
   const int nb = nblocks(c);
   // The reductions are finished by one-workgroup kernels, except that on
   // small lattices (launch-bound: a launch costs a few microseconds) the first
@@ -569,41 +580,48 @@ int launch_iter(qcd_ctx* c, bool mixed) {
   // nb workgroups) finishes right-hand side r, so fusing also needs nb >= nr.
   const bool fuse = nb <= kFuseFinPartials && nb >= c->w->nr;
   if (!mixed) {
-    QCHK(k1_f64(c, V_P, V_T, false, c->w->st));
-    QCHK(k2_f64(c, V_P, V_T, V_Q, false, 1, 0, 0.0, false, c->w->st));
+    const int pj = qcd_ctx::pslot(j);
+    QCHK(k1_f64(c, pj, V_T, false, c->w->st));
+    QCHK(k2_f64(c, pj, V_T, V_Q, false, 1, 0, 0.0, false, c->w->st));
     if (!fuse) HIPCHK(launch_fin_alpha(c->w->st, c->w->partial, nb, c->w->nr, fold_area(c), c->stream));
     QCHK(k1_f64(c, V_Q, V_T, true, c->w->st, fuse));
     QCHK(k2_f64(c, V_Q, V_T, V_R, true, 2, V_R, 0.0, true, c->w->st));
     HIPCHK(launch_fin_beta(c->w->st, c->w->partial, nb, c->w->nr, fold_area(c), c->w->mbox_dev, kRing, c->stream));
-    HIPCHK(launch_xp_update_f64(c->w->gv, c->w->lg, c->w->st, c->f64(V_X), c->f64(V_P), c->f64(V_R), kXpBlock, c->stream));
+    SpF64 p[4];
+    for (int m = 0; m < n; ++m) p[m] = c->f64(qcd_ctx::pslot(m));
+    HIPCHK(launch_xp_update_f64(c->w->gv, c->w->lg, c->w->st, c->f64(V_X), p, j, n, c->f64(V_R), kXpBlock, c->stream));
   } else {
-    QCHK(k1_h(c, H_P, H_T, false, c->w->st));
-    QCHK(k2_h(c, H_P, H_T, H_Q, false, 1, 0, false, c->w->st));
+    const int pj = qcd_ctx::hpslot(j);
+    QCHK(k1_h(c, pj, H_T, false, c->w->st));
+    QCHK(k2_h(c, pj, H_T, H_Q, false, 1, 0, false, c->w->st));
     if (!fuse) HIPCHK(launch_fin_alpha(c->w->st, c->w->partial, nb, c->w->nr, fold_area(c), c->stream));
     QCHK(k1_h(c, H_Q, H_T, true, c->w->st, fuse));
     QCHK(k2_h(c, H_Q, H_T, H_R, true, 2, H_R, true, c->w->st));
     HIPCHK(launch_fin_beta(c->w->st, c->w->partial, nb, c->w->nr, fold_area(c), c->w->mbox_dev, kRing, c->stream));
-    HIPCHK(launch_xp_update_h(c->w->gv, c->w->lg, c->w->st, c->f32(), c->h(H_P), c->h(H_R), kXpBlock, c->stream));
+    SpH p[4];
+    for (int m = 0; m < n; ++m) p[m] = c->h(qcd_ctx::hpslot(m));
+    HIPCHK(launch_xp_update_h(c->w->gv, c->w->lg, c->w->st, c->f32(), p, j, n, c->h(H_R), kXpBlock, c->stream));
   }
   return QCD_OK;
 }
 
 void drop_graphs(qcd_ctx* c) {
-  for (auto& gx : c->iter_graph)
-    if (gx) {
-      (void)hipGraphExecDestroy(gx);
-      gx = nullptr;
-    }
+  for (auto& row : c->iter_graph)
+    for (auto& gx : row)
+      if (gx) {
+        (void)hipGraphExecDestroy(gx);
+        gx = nullptr;
+      }
 }
 
 // Capture one iteration on the private stream into an executable graph.
-int capture_iter(qcd_ctx* c, bool mixed) {
-  hipGraphExec_t& gx = c->iter_graph[mixed ? 1 : 0];
+int capture_iter(qcd_ctx* c, bool mixed, int j) {
+  hipGraphExec_t& gx = c->iter_graph[mixed ? 1 : 0][j];
   if (gx) return QCD_OK;
   const hipStream_t saved = c->stream;
   HIPCHK(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
   c->stream = c->cap;
-  const int rc = launch_iter(c, mixed);
+  const int rc = launch_iter(c, mixed, j);
   c->stream = saved;
   hipGraph_t graph = nullptr;
   const hipError_t e = hipStreamEndCapture(c->cap, &graph);
@@ -620,12 +638,14 @@ int capture_iter(qcd_ctx* c, bool mixed) {
   return QCD_OK;
 }
 
+// Iteration pp.seq of the recurrence is the (pp.seq mod x_defer)-th of its x cycle.
 int enqueue_iter(qcd_ctx* c, Pipe& pp, bool mixed) {
+  const int j = (int)(pp.seq % c->x_defer);
   if (c->use_graph && c->w->lg == 0) {
-    QCHK(capture_iter(c, mixed));
-    HIPCHK(hipGraphLaunch(c->iter_graph[mixed ? 1 : 0], c->stream));
+    QCHK(capture_iter(c, mixed, j));
+    HIPCHK(hipGraphLaunch(c->iter_graph[mixed ? 1 : 0][j], c->stream));
   } else {
-    QCHK(launch_iter(c, mixed));
+    QCHK(launch_iter(c, mixed, j));
   }
   const int slot = next_slot(c);
   HIPCHK(hipEventRecord(c->ev[slot], c->stream));
@@ -635,6 +655,16 @@ int enqueue_iter(qcd_ctx* c, Pipe& pp, bool mixed) {
 }
 
 int pipeline_depth(const qcd_solver_params* p) { return std::min(std::max(1, p->pipeline_depth), kRing / 4); }
+
+// Bytes per site and iteration of the vector work outside the stencils: the
+// residual update in the last stencil's epilogue (read and write r) and the
+// x/p update averaged over the x cycle (n - 1 iterations read p and r and
+// write p; the last also reads the n directions and reads and writes x).
+double xp_bytes_per_iter(const qcd_ctx* c, bool mixed) {
+  const double sp = mixed ? 52.0 : 192.0, xb = mixed ? 96.0 : 192.0;
+  const int n = c->x_defer;
+  return 2 * sp + ((n - 1) * 3 * sp + (n + 2) * sp + 2 * xb) / n;
+}
 
 // FP64 CG on Mhat^dag Mhat x = rhs (V_RHS) into V_X, from x = 0 or (use_x0) from V_X.
 // Work slots: V_R, V_P, V_Q, V_T.
@@ -677,8 +707,19 @@ int cg_fp64(qcd_ctx* c, const qcd_solver_params* p, bool use_x0, CgCounters& cnt
   cnt.iters += s.iter;
   cnt.mdagm += s.iter;
   cnt.restarts += restarts;
-  cnt.blas_bytes += (double)s.iter * 7.0 * 192.0 * c->w->gv.Vh;
+  cnt.blas_bytes += (double)s.iter * xp_bytes_per_iter(c, false) * c->w->gv.Vh;
   return QCD_OK;
+}
+
+// x_hi += x_lo + the directions of the x cycle that the iterations enqueued
+// so far left pending (the first q = pp.seq mod x_defer of the cycle);
+// x_lo = 0.  Returns q (>= 0) or a negative status.
+int fold_x(qcd_ctx* c, const Pipe& pp) {
+  const int q = (int)(pp.seq % c->x_defer);
+  SpH p[4];
+  for (int m = 0; m < q; ++m) p[m] = c->h(qcd_ctx::hpslot(m));
+  HIPCHK(launch_ru_accum(c->w->gv, c->w->lg, c->w->st, c->f64(V_X), c->f32(), p, q, c->block(), c->stream));
+  return q;
 }
 
 // Mixed-precision CG with reliable updates.  Inner recurrence on binary16
@@ -717,7 +758,7 @@ int cg_mixed(qcd_ctx* c, const qcd_solver_params* p, CgCounters& cnt) {
         stall = 0;
       } else if (++stall >= 3) {
         HIPCHK(hipStreamSynchronize(c->stream));
-        HIPCHK(launch_ru_accum(c->w->gv, c->f64(V_X), c->f32(), B, c->stream));
+        if (const int q = fold_x(c, pp); q < 0) return q;
         cnt.iters += s.iter;
         cnt.mdagm_mixed += s.iter;
         cnt.restarts += 1;
@@ -727,9 +768,11 @@ int cg_mixed(qcd_ctx* c, const qcd_solver_params* p, CgCounters& cnt) {
       }
     }
     if (s.need_ru && idx >= ru_barrier) {
-      // fold x_lo into x_hi, r = rhs - A x_hi in FP64, re-encode r; p is kept
-      HIPCHK(launch_ru_accum(c->w->gv, c->f64(V_X), c->f32(), B, c->stream));
-      QCHK(recompute_residual(c, 0, nullptr));
+      // fold x_lo and the unfinished x cycle into x_hi, r = rhs - A x_hi in
+      // FP64, re-encode r; p is kept
+      const int q = fold_x(c, pp);
+      if (q < 0) return q;
+      QCHK(recompute_residual(c, 0, nullptr, q));
       HIPCHK(launch_convert(c->w->gv, c->ref64(V_R), c->refh(H_R), B, c->stream));
       cnt.mdagm += 1;
       cnt.ru += 1;
@@ -739,7 +782,7 @@ int cg_mixed(qcd_ctx* c, const qcd_solver_params* p, CgCounters& cnt) {
   HIPCHK(hipStreamSynchronize(c->stream));
   cnt.iters += s.iter;
   cnt.mdagm_mixed += s.iter;
-  cnt.blas_bytes += (double)s.iter * (2 * 52.0 + 3 * 52.0 + 2 * 96.0) * c->w->gv.Vh;
+  cnt.blas_bytes += (double)s.iter * xp_bytes_per_iter(c, true) * c->w->gv.Vh;
   return QCD_OK;
 }
 
@@ -926,6 +969,10 @@ int qcd_set_option(qcd_ctx* c, int option, int value) {
     case QCD_OPT_MIXED_STALL:
       if (value < 1 || value > 60) return fail(QCD_EINVAL, "mixed stall exponent must lie in [1, 60]");
       c->stall_log2 = value;
+      return QCD_OK;
+    case QCD_OPT_X_CYCLE:
+      if (value < 1 || value > 4) return fail(QCD_EINVAL, "x cycle must lie in [1, 4]");
+      c->x_defer = value;
       return QCD_OK;
     default:
       return fail(QCD_EINVAL, "unknown option");

@@ -310,6 +310,7 @@ __global__ void fin_init_k(CgState* st, const double* partial, int n, double tol
   st->do_p = 0;
   st->mixed = mixed;
   st->ru_count = 0;
+  for (int m = 0; m < 4; ++m) st->ah[m] = 0.0;
   post(st, mbox, ring);
 }
 __global__ void fin_alpha_k(CgState* st, const double* partial, int n) {
@@ -333,12 +334,17 @@ __global__ void fin_beta_k(CgState* st, const double* partial, int n, CgState* m
 // After an FP64 residual recomputation r = rhs - A x (partials of |r|^2):
 //   restart = 0 (reliable update): r replaces the recurrence residual, p is kept;
 //   restart = 1 (CG restart): beta = 0, so the following p update sets p = r.
-__global__ void fin_ru_k(CgState* st, const double* partial, int n, int restart, CgState* mbox, int ring) {
+// The newest nclear alphas of the history were already taken into x (the
+// reliable update folded the unfinished cycle's directions in): they are
+// zeroed, so the end of the cycle does not add those directions again.
+__global__ void fin_ru_k(CgState* st, const double* partial, int n, int restart, int nclear, CgState* mbox,
+                         int ring) {
   st += blockIdx.x;
   partial += (size_t)blockIdx.x * n;
   mbox += (size_t)blockIdx.x * ring;
   const double rr = block_sum_partials(partial, n);
   if (threadIdx.x != 0) return;
+  for (int m = 0; m < nclear && m < 4; ++m) st->ah[m] = 0.0;
   st->rr_hi = rr;
   st->ru_count += 1;
   st->need_ru = 0;
@@ -395,83 +401,131 @@ hipError_t launch_fin_beta(CgState* st, const double* partial, int n, int nr, do
                            hipStream_t s) {
   FIN_LAUNCH(fin_beta_k, st, partial, n, mbox, ring)
 }
-hipError_t launch_fin_ru(CgState* st, const double* partial, int n, int nr, double* fold, int restart, CgState* mbox,
-                         int ring, hipStream_t s) {
-  FIN_LAUNCH(fin_ru_k, st, partial, n, restart, mbox, ring)
+hipError_t launch_fin_ru(CgState* st, const double* partial, int n, int nr, double* fold, int restart, int nclear,
+                         CgState* mbox, int ring, hipStream_t s) {
+  FIN_LAUNCH(fin_ru_k, st, partial, n, restart, nclear, mbox, ring)
 }
 
 // ------------------------------------------------------------------ CG vector updates
-// x += alpha p; then p = r + beta p unless the recurrence stopped.
+// The solution takes each search direction a few iterations late: over a
+// cycle of n iterations (n = 1 .. 4) the directions p_0 .. p_{n-1} live in
+// buffers of their own, and x += alpha_0 p_0 + ... + alpha_{n-1} p_{n-1} is
+// done once, at the end of the cycle, instead of reading and writing x every
+// iteration.  Iteration j of the cycle (its direction p_j in `pc`, the older
+// ones p_{j-1} .. p_0 in `old`, newest first) sets p_{j+1} = r + beta p_j in
+// `pout`; x takes sum_{m <= j} ah[m] p_{j-m} at the end of the cycle (`last`)
+// or when the recurrence stops at this iteration (do_p == 0), so every
+// direction reaches x once.  ah[] is the state's alpha history, newest first.
 // Element i belongs to right-hand side i & ((1 << lg) - 1) and uses its state.
-__global__ void __launch_bounds__(256) xp_update_f64_k(Geom g, int lg, const CgState* st, SpF64 x, SpF64 p,
-                                                       SpF64 r) {
+template <class Sp>
+struct Older {
+  Sp p[3];
+};
+
+template <int NOLD>
+__global__ void __launch_bounds__(256) xp_update_f64_k(Geom g, int lg, const CgState* st, SpF64 x, SpF64 pc,
+                                                       Older<SpF64> old, SpF64 pout, SpF64 r, int last) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   st += i & ((1 << lg) - 1);
   if (!st->do_x) return;
   if (i >= g.Vh) return;
-  const double al = st->alpha, be = st->beta;
+  const double be = st->beta;
   const bool dp = st->do_p;
+  const bool dx = last || !dp;
+  double a[NOLD + 1];
+#pragma unroll
+  for (int m = 0; m <= NOLD; ++m) a[m] = st->ah[m];
 #pragma unroll
   for (int k = 0; k < 12; ++k) {
     const size_t o = (size_t)k * g.stride + i;
-    const double2 pv = p.p[o];
-    double2 xv = x.p[o];
-    xv.x += al * pv.x;
-    xv.y += al * pv.y;
-    x.p[o] = xv;
+    const double2 pv = pc.p[o];
+    if (dx) {
+      double2 acc = make_double2(a[0] * pv.x, a[0] * pv.y);
+#pragma unroll
+      for (int m = 1; m <= NOLD; ++m) {
+        const double2 q = old.p[m - 1].p[o];
+        acc.x += a[m] * q.x;
+        acc.y += a[m] * q.y;
+      }
+      double2 xv = x.p[o];
+      xv.x += acc.x;
+      xv.y += acc.y;
+      x.p[o] = xv;
+    }
     if (dp) {
       const double2 rv = r.p[o];
-      p.p[o] = make_double2(rv.x + be * pv.x, rv.y + be * pv.y);
+      pout.p[o] = make_double2(rv.x + be * pv.x, rv.y + be * pv.y);
     }
   }
 }
+// CG restart (beta is zero after one): p = r where the recurrence continues.
 __global__ void __launch_bounds__(256) p_restart_f64_k(Geom g, int lg, const CgState* st, SpF64 p, SpF64 r) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   st += i & ((1 << lg) - 1);
   if (!st->do_p) return;
   if (i >= g.Vh) return;
-  const double be = st->beta;
 #pragma unroll
   for (int k = 0; k < 12; ++k) {
     const size_t o = (size_t)k * g.stride + i;
-    const double2 rv = r.p[o];
-    if (be == 0.0) {
-      p.p[o] = rv;
-    } else {
-      const double2 pv = p.p[o];
-      p.p[o] = make_double2(rv.x + be * pv.x, rv.y + be * pv.y);
-    }
+    p.p[o] = r.p[o];
   }
 }
-// mixed: x (FP32) += alpha p (binary16); p = r + beta p, re-encoded.
-__global__ void __launch_bounds__(256) xp_update_h_k(Geom g, int lg, const CgState* st, SpF32 x, SpH p, SpH r) {
+// mixed: the same cycle with x in FP32 and the directions in binary16
+// (re-encoded per site when written).
+template <int NOLD>
+__global__ void __launch_bounds__(256) xp_update_h_k(Geom g, int lg, const CgState* st, SpF32 x, SpH pc,
+                                                     Older<SpH> old, SpH pout, SpH r, int last) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   st += i & ((1 << lg) - 1);
   if (!st->do_x) return;
   if (i >= g.Vh) return;
-  const float al = float(st->alpha), be = float(st->beta);
-  Spinor<float> pv, xv;
-  load(p, i, pv);
-  load(x, i, xv);
+  const float be = float(st->beta);
+  const bool dp = st->do_p;
+  Spinor<float> pv;
+  load(pc, i, pv);
+  if (last || !dp) {
+    Spinor<float> acc, xv;
+    const float a0 = float(st->ah[0]);
 #pragma unroll
-  for (int s = 0; s < 4; ++s)
+    for (int s = 0; s < 4; ++s)
 #pragma unroll
-    for (int c = 0; c < 3; ++c) xv.v[s][c] = xv.v[s][c] + al * pv.v[s][c];
-  store(x, i, xv);
-  if (st->do_p) {
+      for (int c = 0; c < 3; ++c) acc.v[s][c] = a0 * pv.v[s][c];
+#pragma unroll
+    for (int m = 1; m <= NOLD; ++m) {
+      const float am = float(st->ah[m]);
+      Spinor<float> q;
+      load(old.p[m - 1], i, q);
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) acc.v[s][c] = acc.v[s][c] + am * q.v[s][c];
+    }
+    load(x, i, xv);
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) xv.v[s][c] = xv.v[s][c] + acc.v[s][c];
+    store(x, i, xv);
+  }
+  if (dp) {
     Spinor<float> rv;
     load(r, i, rv);
 #pragma unroll
     for (int s = 0; s < 4; ++s)
 #pragma unroll
       for (int c = 0; c < 3; ++c) rv.v[s][c] = rv.v[s][c] + be * pv.v[s][c];
-    store(p, i, rv);
+    store(pout, i, rv);
   }
 }
-// x_hi += x_lo; x_lo = 0
-__global__ void __launch_bounds__(256) ru_accum_k(Geom g, SpF64 xhi, SpF32 xlo) {
+// Reliable update: x_hi += x_lo + the directions of the unfinished cycle
+// (pend.p[m] = p_{q-1-m} with weight ah[m], m < NQ, for right-hand sides whose
+// last iteration ran); x_lo = 0.  The sum is taken in FP64.
+template <int NQ>
+__global__ void __launch_bounds__(256) ru_accum_k(Geom g, int lg, const CgState* st, SpF64 xhi, SpF32 xlo,
+                                                  Older<SpH> pend) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= g.Vh) return;
+  st += i & ((1 << lg) - 1);
   Spinor<double> a, b;
   load(xhi, i, a);
   load(xlo, i, b);
@@ -479,15 +533,49 @@ __global__ void __launch_bounds__(256) ru_accum_k(Geom g, SpF64 xhi, SpF32 xlo) 
   for (int s = 0; s < 4; ++s)
 #pragma unroll
     for (int c = 0; c < 3; ++c) a.v[s][c] = a.v[s][c] + b.v[s][c];
+  if (NQ > 0 && st->do_x) {
+#pragma unroll
+    for (int m = 0; m < NQ; ++m) {
+      const double am = st->ah[m];
+      Spinor<float> q;
+      load(pend.p[m], i, q);
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const Cx<float> v = q.v[s][c];
+          a.v[s][c] = a.v[s][c] + am * Cx<double>{double(v.re), double(v.im)};
+        }
+    }
+  }
   store(xhi, i, a);
   Spinor<float> z;
   zero(z);
   store(xlo, i, z);
 }
 
-hipError_t launch_xp_update_f64(const Geom& gv, int lg, const CgState* st, SpF64 x, SpF64 p, SpF64 r, int block,
-                                hipStream_t s) {
-  hipLaunchKernelGGL(xp_update_f64_k, dim3(blocks_for(gv.Vh, block)), dim3(block), 0, s, gv, lg, st, x, p, r);
+namespace {
+template <class Sp>
+Older<Sp> older_of(const Sp* p, int j) {
+  Older<Sp> o{};
+  for (int m = 1; m <= j; ++m) o.p[m - 1] = p[j - m];
+  return o;
+}
+}  // namespace
+
+hipError_t launch_xp_update_f64(const Geom& gv, int lg, const CgState* st, SpF64 x, const SpF64* p, int j, int n,
+                                SpF64 r, int block, hipStream_t s) {
+  if (n < 1 || n > 4 || j < 0 || j >= n) return hipErrorInvalidValue;
+  const dim3 grid(blocks_for(gv.Vh, block));
+  const Older<SpF64> o = older_of(p, j);
+  const SpF64 pout = p[(j + 1) % n];
+  const int last = j == n - 1;
+  switch (j) {
+    case 0: hipLaunchKernelGGL(xp_update_f64_k<0>, grid, dim3(block), 0, s, gv, lg, st, x, p[j], o, pout, r, last); break;
+    case 1: hipLaunchKernelGGL(xp_update_f64_k<1>, grid, dim3(block), 0, s, gv, lg, st, x, p[j], o, pout, r, last); break;
+    case 2: hipLaunchKernelGGL(xp_update_f64_k<2>, grid, dim3(block), 0, s, gv, lg, st, x, p[j], o, pout, r, last); break;
+    default: hipLaunchKernelGGL(xp_update_f64_k<3>, grid, dim3(block), 0, s, gv, lg, st, x, p[j], o, pout, r, last); break;
+  }
   return hipGetLastError();
 }
 hipError_t launch_p_restart_f64(const Geom& gv, int lg, const CgState* st, SpF64 p, SpF64 r, int block,
@@ -495,13 +583,33 @@ hipError_t launch_p_restart_f64(const Geom& gv, int lg, const CgState* st, SpF64
   hipLaunchKernelGGL(p_restart_f64_k, dim3(blocks_for(gv.Vh, block)), dim3(block), 0, s, gv, lg, st, p, r);
   return hipGetLastError();
 }
-hipError_t launch_xp_update_h(const Geom& gv, int lg, const CgState* st, SpF32 x, SpH p, SpH r, int block,
-                              hipStream_t s) {
-  hipLaunchKernelGGL(xp_update_h_k, dim3(blocks_for(gv.Vh, block)), dim3(block), 0, s, gv, lg, st, x, p, r);
+hipError_t launch_xp_update_h(const Geom& gv, int lg, const CgState* st, SpF32 x, const SpH* p, int j, int n, SpH r,
+                              int block, hipStream_t s) {
+  if (n < 1 || n > 4 || j < 0 || j >= n) return hipErrorInvalidValue;
+  const dim3 grid(blocks_for(gv.Vh, block));
+  const Older<SpH> o = older_of(p, j);
+  const SpH pout = p[(j + 1) % n];
+  const int last = j == n - 1;
+  switch (j) {
+    case 0: hipLaunchKernelGGL(xp_update_h_k<0>, grid, dim3(block), 0, s, gv, lg, st, x, p[j], o, pout, r, last); break;
+    case 1: hipLaunchKernelGGL(xp_update_h_k<1>, grid, dim3(block), 0, s, gv, lg, st, x, p[j], o, pout, r, last); break;
+    case 2: hipLaunchKernelGGL(xp_update_h_k<2>, grid, dim3(block), 0, s, gv, lg, st, x, p[j], o, pout, r, last); break;
+    default: hipLaunchKernelGGL(xp_update_h_k<3>, grid, dim3(block), 0, s, gv, lg, st, x, p[j], o, pout, r, last); break;
+  }
   return hipGetLastError();
 }
-hipError_t launch_ru_accum(const Geom& g, SpF64 xhi, SpF32 xlo, int block, hipStream_t s) {
-  hipLaunchKernelGGL(ru_accum_k, dim3(blocks_for(g.Vh, block)), dim3(block), 0, s, g, xhi, xlo);
+hipError_t launch_ru_accum(const Geom& gv, int lg, const CgState* st, SpF64 xhi, SpF32 xlo, const SpH* p, int q,
+                           int block, hipStream_t s) {
+  if (q < 0 || q > 3) return hipErrorInvalidValue;
+  const dim3 grid(blocks_for(gv.Vh, block));
+  Older<SpH> pend{};
+  for (int m = 0; m < q; ++m) pend.p[m] = p[q - 1 - m];
+  switch (q) {
+    case 0: hipLaunchKernelGGL(ru_accum_k<0>, grid, dim3(block), 0, s, gv, lg, st, xhi, xlo, pend); break;
+    case 1: hipLaunchKernelGGL(ru_accum_k<1>, grid, dim3(block), 0, s, gv, lg, st, xhi, xlo, pend); break;
+    case 2: hipLaunchKernelGGL(ru_accum_k<2>, grid, dim3(block), 0, s, gv, lg, st, xhi, xlo, pend); break;
+    default: hipLaunchKernelGGL(ru_accum_k<3>, grid, dim3(block), 0, s, gv, lg, st, xhi, xlo, pend); break;
+  }
   return hipGetLastError();
 }
 

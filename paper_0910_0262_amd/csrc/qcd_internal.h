@@ -23,6 +23,7 @@ struct CgState {
   double delta2;   // delta_reliable^2
   double rr_hi;    // last FP64 residual norm^2
   double scalar;   // generic reduction result (dot products, norms)
+  double ah[4];    // the last four alphas, newest first (x takes alpha_k p_k a few iterations late)
   int iter, max_iter;
   int halt, done, need_ru, nan, do_x, do_p, mixed, ru_count;
   int post_seq;    // number of states posted so far; the next goes to mailbox[post_seq % ring]
@@ -42,17 +43,22 @@ __device__ __forceinline__ void post(CgState* st, CgState* mbox, int ring) {
   __threadfence_system();
 }
 
-// alpha = |r|^2 / |Mhat p|^2
+// alpha = |r|^2 / |Mhat p|^2, also shifted into the alpha history
 __device__ __forceinline__ void state_alpha(CgState* st, double qq) {
   st->qq = qq;
+  st->ah[3] = st->ah[2];
+  st->ah[2] = st->ah[1];
+  st->ah[1] = st->ah[0];
   if (!(qq > 0.0) || !finite(qq)) {
     st->nan = 1;
     st->done = 1;
     st->halt = 1;
     st->alpha = 0.0;
+    st->ah[0] = 0.0;
     return;
   }
   st->alpha = st->rr / qq;
+  st->ah[0] = st->alpha;
 }
 
 // End of an iteration: |r_{k+1}|^2, beta, the stopping test (FP64) or the
@@ -185,15 +191,18 @@ hipError_t launch_fin_init(CgState* st, const double* partial, int n, int nr, do
 hipError_t launch_fin_alpha(CgState* st, const double* partial, int n, int nr, double* fold, hipStream_t s);
 hipError_t launch_fin_beta(CgState* st, const double* partial, int n, int nr, double* fold, CgState* mbox, int ring,
                            hipStream_t s);
-hipError_t launch_fin_ru(CgState* st, const double* partial, int n, int nr, double* fold, int restart, CgState* mbox,
-                         int ring, hipStream_t s);
-hipError_t launch_xp_update_f64(const Geom& gv, int lg, const CgState* st, SpF64 x, SpF64 p, SpF64 r, int block,
-                                hipStream_t s);
-hipError_t launch_xp_update_h(const Geom& gv, int lg, const CgState* st, SpF32 x, SpH p, SpH r, int block,
-                              hipStream_t s);
+hipError_t launch_fin_ru(CgState* st, const double* partial, int n, int nr, double* fold, int restart, int nclear,
+                         CgState* mbox, int ring, hipStream_t s);
+// Iteration j of an n-iteration x cycle; p[0 .. n-1] are the cycle's direction buffers.
+hipError_t launch_xp_update_f64(const Geom& gv, int lg, const CgState* st, SpF64 x, const SpF64* p, int j, int n,
+                                SpF64 r, int block, hipStream_t s);
+hipError_t launch_xp_update_h(const Geom& gv, int lg, const CgState* st, SpF32 x, const SpH* p, int j, int n, SpH r,
+                              int block, hipStream_t s);
 hipError_t launch_p_restart_f64(const Geom& gv, int lg, const CgState* st, SpF64 p, SpF64 r, int block,
                                 hipStream_t s);
-hipError_t launch_ru_accum(const Geom& g, SpF64 xhi, SpF32 xlo, int block, hipStream_t s);
+// x_hi += x_lo + the first q directions p[0 .. q-1] of the unfinished cycle; x_lo = 0
+hipError_t launch_ru_accum(const Geom& gv, int lg, const CgState* st, SpF64 xhi, SpF32 xlo, const SpH* p, int q,
+                           int block, hipStream_t s);
 hipError_t launch_convert(const Geom& g, SpRef src, SpRef dst, int block, hipStream_t s);
 hipError_t launch_zero(const Geom& g, SpRef x, int block, hipStream_t s);
 hipError_t launch_encode_half(int n, const double2* user, uint4* codes, float* scale, hipStream_t s);

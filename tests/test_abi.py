@@ -42,7 +42,8 @@ def test_header_is_plain_c():
 def test_options_match_the_header():
     text = open(HEADER).read()
     for name in ("QCD_OPT_LINK_RECON", "QCD_OPT_MIXED_CLOVER", "QCD_OPT_BLOCK", "QCD_OPT_GRAPH",
-                 "QCD_OPT_SMALL_GRID", "QCD_OPT_MIXED_STALL", "QCD_OPT_COMPACT_CLOVER"):
+                 "QCD_OPT_SMALL_GRID", "QCD_OPT_MIXED_STALL", "QCD_OPT_COMPACT_CLOVER",
+                 "QCD_OPT_X_CYCLE"):
         m = re.search(rf"\b{name}\s*=\s*(\d+)", text)
         assert m and int(m.group(1)) == getattr(capi, name), name
 

@@ -55,6 +55,25 @@ def test_multi_solve_parity(case, prec, n):
         assert float(torch.linalg.norm(r) / torch.linalg.norm(torch.as_tensor(bs[j]))) < 1e-10
 
 
+@pytest.mark.parametrize("cycle", [1, 3])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_multi_x_cycles(case, prec, cycle):
+    """Five right-hand sides converge at different iterations, so with x cycles
+    of 3 (and 4, the default, in the solve test above) each FP64 recurrence
+    stops at its own position in the cycle and takes its pending directions
+    there; every solution meets the oracle's bar."""
+    dims, lat, setup, bs, refs = case
+    lat.set_option(capi.QCD_OPT_X_CYCLE, cycle)
+    try:
+        x, sts = lat.solve_multi(to_dev(bs), prec=prec, tol=1e-12)
+    finally:
+        lat.set_option(capi.QCD_OPT_X_CYCLE, 4)
+    print(f"  {prec} cycle={cycle}: iters={[s['iters'] for s in sts]}", flush=True)
+    for j in range(len(bs)):
+        assert sts[j]["converged"] == 1 and sts[j]["true_rel_res"] < 1e-10
+        assert rel_err(x[j], refs[j]) < 1e-10, j
+
+
 def test_multi_matches_single_and_is_deterministic(case):
     dims, lat, setup, bs, refs = case
     b = to_dev(bs[:4])

@@ -156,18 +156,23 @@ def test_zero_source():
     lat.close()
 
 
-def test_mixed_fallback_to_fp64(case):
+@pytest.mark.parametrize("cycle", [1, 3, 4])
+def test_mixed_fallback_to_fp64(case, cycle):
     """QCD_OPT_MIXED_STALL = 40 asks every reliable update to cut the FP64 |r|^2 to
     2^-40 of its best; at delta 0.1 each cuts it by about a hundred, so the first
     three reliable updates (a fall of about 1e-6) count as stalled and the solve
     finishes in FP64 CG from the accumulated solution: one restart, converged,
-    and the oracle's bar.  The default (k = 1, halving) never falls back here."""
+    and the oracle's bar.  The default (k = 1, halving) never falls back here.
+    With x cycles of 3 and 4 (the default) the fallback may come inside a
+    cycle, whose directions the accumulated solution must then take."""
     dims, lat, setup, b, ref = case
     lat.set_option(capi.QCD_OPT_MIXED_STALL, 40)
+    lat.set_option(capi.QCD_OPT_X_CYCLE, cycle)
     try:
         x, st = lat.solve(to_dev(b), prec="mixed", tol=1e-12)
     finally:
         lat.set_option(capi.QCD_OPT_MIXED_STALL, 1)
+        lat.set_option(capi.QCD_OPT_X_CYCLE, 4)
     print(f"  fallback: iters={st['iters']} ru={st['reliable_updates']} restarts={st['restarts']}", flush=True)
     assert st["restarts"] == 1 and st["converged"] == 1
     assert 3 <= st["reliable_updates"] <= 4
@@ -177,3 +182,70 @@ def test_mixed_fallback_to_fp64(case):
     for bad in (0, 61):
         with pytest.raises(QCDError, match="EINVAL"):
             lat.set_option(capi.QCD_OPT_MIXED_STALL, bad)
+
+
+# ---------------------------------------------------------------- x cycles
+@pytest.mark.parametrize("cycle", [1, 2, 3])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_x_cycle_solve_parity(case, prec, cycle):
+    """QCD_OPT_X_CYCLE = n keeps the search directions of n iterations and updates
+    x once per n; the mixed solver's reliable updates (at least five here, so
+    some fall inside a cycle for n > 1) fold the pending directions in.  Every
+    n meets the oracle's bar (the default, 4, is the solve test above)."""
+    dims, lat, setup, b, ref = case
+    lat.set_option(capi.QCD_OPT_X_CYCLE, cycle)
+    try:
+        x, st = lat.solve(to_dev(b), prec=prec, tol=1e-12)
+    finally:
+        lat.set_option(capi.QCD_OPT_X_CYCLE, 4)
+    print(f"  {prec} cycle={cycle}: iters={st['iters']} ru={st['reliable_updates']}", flush=True)
+    assert st["converged"] == 1 and st["restarts"] == 0
+    assert rel_err(x, ref.x) < 1e-10 and st["true_rel_res"] < 1e-10
+    if prec == "mixed":
+        assert st["reliable_updates"] >= 5
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_x_cycle_stopped_at_every_position(prec):
+    """Capped at m = 1 .. 9 iterations, the recurrence stops at every position of
+    cycles of 2, 3 and 4 iterations (the mixed solver, with two iterations in
+    flight, runs m + 1 and folds the unfinished cycle in at its one reliable
+    update).  The recurrence (r, p, alpha, beta) reads x only at a reliable
+    update, and delta_reliable = 1e-6 allows none before the cap, so the iterate
+    must equal that of cycle 1 (x updated every iteration) up to the rounding
+    of the sums (FP64; FP32 for the mixed x_lo): a direction dropped or taken
+    twice would move it by alpha_k p_k, which at these m is far larger (checked:
+    consecutive m differ by much more than the bar)."""
+    dims = (4, 4, 4, 4)
+    lat, setup, u, ud = make_case(dims, 0.3, 0.12, 1.0, 0)
+    b = to_dev(synth.gaussian_source(dims, 0, 0))
+    bar = 1e-13 if prec == "fp64" else 1e-6
+    prev = None
+    try:
+        for m in range(1, 10):
+            xs = {}
+            for cyc in (1, 2, 3, 4):
+                lat.set_option(capi.QCD_OPT_X_CYCLE, cyc)
+                xs[cyc], st = lat.solve(b, prec=prec, tol=1e-14, max_iter=m, delta_reliable=1e-6,
+                                        raise_on_noconv=False)
+                assert st["status"] == "QCD_ENOCONV"
+                if prec == "fp64":
+                    assert st["iters"] == m
+                else:
+                    assert st["reliable_updates"] == 1
+            for cyc in (2, 3, 4):
+                assert rel_err(xs[cyc], xs[1]) < bar, (m, cyc)
+            if prev is not None:
+                assert rel_err(xs[1], prev) > 1e3 * bar, m
+            prev = xs[1]
+    finally:
+        lat.set_option(capi.QCD_OPT_X_CYCLE, 4)
+        lat.close()
+
+
+def test_x_cycle_rejects_out_of_range():
+    lat = Lattice((4, 4, 4, 4), 0.12, 1.0)
+    for bad in (0, 5, -1):
+        with pytest.raises(QCDError, match="EINVAL"):
+            lat.set_option(capi.QCD_OPT_X_CYCLE, bad)
+    lat.close()
