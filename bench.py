@@ -50,7 +50,7 @@ TRAFFIC_KERNELS = {
     "k1_mixed_multi": ("dslash_kernel<float, 0, true, false, true,", "LinkH18", "CloverH>"),
     "k1_mixed_single": ("dslash_kernel<float, 0, true, false, false,", "LinkH12", "CloverH>"),
 }
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_0910_0262_amd", "csrc", f) for f in ("qcd_device.h", "dslash.hip")]
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_0910_0262_amd", "csrc", f) for f in ("qcd_device.h", "qcd_internal.h", "dslash.hip")]
 
 
 def log(msg: str) -> None:
