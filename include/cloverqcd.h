@@ -273,7 +273,7 @@ int qcd_gauge_action_force(qcd_ctx *ctx, double beta, double *S, void *G_dev, do
  * both; the action itself is not computed (it needs a host synchronisation).
  * It calls no allocator: the force accumulator lives in a fixed 64 MiB
  * device array of the library, one per GPU, so the lattice is limited to
- * V <= 116508 sites (QCD_EINVAL beyond, before any device work; 16^4 and
+ * V <= 116480 sites (QCD_EINVAL beyond, before any device work; 16^4 and
  * 8x8x16x16 fit, 32^3x64 does not).  Stream-ordered: returns once the two
  * kernels are enqueued on the context's stream, without waiting.  Every call
  * on one GPU uses the same array: calls that overlap on one GPU (contexts on

@@ -871,7 +871,7 @@ int qcd_create(const int dims[4], int device, uintptr_t hip_stream, qcd_ctx** ou
   g.Xh = dims[0] / 2;
   g.V = dims[0] * dims[1] * dims[2] * dims[3];
   g.Vh = g.V / 2;
-  g.stride = g.Vh;
+  g.stride = (g.Vh + 63) & ~63;  // FP64 spinor fields are tiled by 64 elements
   g.tb = c->tb;
   g.inv_xh = 1.0 / g.Xh;
   g.inv_y = 1.0 / g.X[1];

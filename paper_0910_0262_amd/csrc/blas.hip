@@ -20,7 +20,7 @@ __global__ void pack_spinor_full_k(Geom g, const double2* __restrict__ user, SpF
   const SpF64 f = parity_of(x) ? o : e;
   const int cb = i >> 1;
 #pragma unroll
-  for (int k = 0; k < 12; ++k) f.p[(size_t)k * f.stride + cb] = user[(size_t)i * 12 + k];
+  for (int k = 0; k < 12; ++k) f.p[sp64_at(k, cb)] = user[(size_t)i * 12 + k];
 }
 __global__ void unpack_spinor_full_k(Geom g, SpF64 e, SpF64 o, double2* __restrict__ user) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -30,19 +30,19 @@ __global__ void unpack_spinor_full_k(Geom g, SpF64 e, SpF64 o, double2* __restri
   const SpF64 f = parity_of(x) ? o : e;
   const int cb = i >> 1;
 #pragma unroll
-  for (int k = 0; k < 12; ++k) user[(size_t)i * 12 + k] = f.p[(size_t)k * f.stride + cb];
+  for (int k = 0; k < 12; ++k) user[(size_t)i * 12 + k] = f.p[sp64_at(k, cb)];
 }
 __global__ void pack_spinor_cb_k(int n, const double2* __restrict__ user, SpF64 f) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
 #pragma unroll
-  for (int k = 0; k < 12; ++k) f.p[(size_t)k * f.stride + i] = user[(size_t)i * 12 + k];
+  for (int k = 0; k < 12; ++k) f.p[sp64_at(k, i)] = user[(size_t)i * 12 + k];
 }
 __global__ void unpack_spinor_cb_k(int n, SpF64 f, double2* __restrict__ user) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
 #pragma unroll
-  for (int k = 0; k < 12; ++k) user[(size_t)i * 12 + k] = f.p[(size_t)k * f.stride + i];
+  for (int k = 0; k < 12; ++k) user[(size_t)i * 12 + k] = f.p[sp64_at(k, i)];
 }
 
 // n right-hand sides [n][V][12] -> interleaved fields, element (cb << lg) | r;
@@ -57,7 +57,7 @@ __global__ void pack_spinor_multi_k(Geom g, int lg, int n, const double2* __rest
   const size_t v = ((size_t)(i >> 1) << lg) | r;
 #pragma unroll
   for (int k = 0; k < 12; ++k)
-    f.p[(size_t)k * f.stride + v] = r < n ? user[((size_t)r * g.V + i) * 12 + k] : make_double2(0.0, 0.0);
+    f.p[sp64_at(k, v)] = r < n ? user[((size_t)r * g.V + i) * 12 + k] : make_double2(0.0, 0.0);
 }
 __global__ void unpack_spinor_multi_k(Geom g, int lg, int n, SpF64 e, SpF64 o, double2* __restrict__ user) {
   const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -69,7 +69,7 @@ __global__ void unpack_spinor_multi_k(Geom g, int lg, int n, SpF64 e, SpF64 o, d
   const SpF64 f = parity_of(x) ? o : e;
   const size_t v = ((size_t)(i >> 1) << lg) | r;
 #pragma unroll
-  for (int k = 0; k < 12; ++k) user[((size_t)r * g.V + i) * 12 + k] = f.p[(size_t)k * f.stride + v];
+  for (int k = 0; k < 12; ++k) user[((size_t)r * g.V + i) * 12 + k] = f.p[sp64_at(k, v)];
 }
 hipError_t launch_pack_spinor_multi(const Geom& g, int lg, int n, const double2* user, SpF64 e, SpF64 o,
                                     hipStream_t s) {
@@ -247,7 +247,7 @@ __global__ void __launch_bounds__(256) dot_re_k(Geom gv, int lg, SpF64 a, SpF64 
   if (i < gv.Vh) {
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
-      const double2 u = a.p[(size_t)k * a.stride + i], v = b.p[(size_t)k * b.stride + i];
+      const double2 u = a.p[sp64_at(k, i)], v = b.p[sp64_at(k, i)];
       n += u.x * v.x + u.y * v.y;
     }
   }
@@ -437,7 +437,7 @@ __global__ void __launch_bounds__(256) xp_update_f64_k(Geom g, int lg, const CgS
   for (int m = 0; m <= NOLD; ++m) a[m] = st->ah[m];
 #pragma unroll
   for (int k = 0; k < 12; ++k) {
-    const size_t o = (size_t)k * g.stride + i;
+    const size_t o = sp64_at(k, i);
     const double2 pv = pc.p[o];
     if (dx) {
       double2 acc = make_double2(a[0] * pv.x, a[0] * pv.y);
@@ -466,7 +466,7 @@ __global__ void __launch_bounds__(256) p_restart_f64_k(Geom g, int lg, const CgS
   if (i >= g.Vh) return;
 #pragma unroll
   for (int k = 0; k < 12; ++k) {
-    const size_t o = (size_t)k * g.stride + i;
+    const size_t o = sp64_at(k, i);
     p.p[o] = r.p[o];
   }
 }

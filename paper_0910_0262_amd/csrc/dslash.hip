@@ -300,7 +300,7 @@ template <int H, typename R>
 __device__ __forceinline__ void load_half(const SpF64& f, int i, Cx<R> v[6]) {
 #pragma unroll
   for (int j = 0; j < 6; ++j) {
-    const double2 d = ld_stream(elem(f.p, (size_t)(6 * H + j) * f.stride, i));
+    const double2 d = ld_stream(f.p + sp64_at(6 * H + j, i));
     v[j] = {R(d.x), R(d.y)};
   }
 }
@@ -329,7 +329,7 @@ __device__ __forceinline__ void store_half(const SpF64& f, int i, const Cx<R> v[
 #pragma unroll
   for (int j = 0; j < 6; ++j) {
     const nt_d2 w = {double(v[j].re), double(v[j].im)};
-    __builtin_nontemporal_store(w, (nt_d2*)elem(f.p, (size_t)(6 * H + j) * f.stride, i));
+    __builtin_nontemporal_store(w, (nt_d2*)(f.p + sp64_at(6 * H + j, i)));
   }
 }
 // m: the site's max |component| over both halves, as the one-work-item encoder takes it

@@ -354,11 +354,17 @@ __device__ __forceinline__ unsigned int ld_stream(const unsigned int* p) { retur
 // ------------------------------------------------------------------ spinor fields
 // Each field is one checkerboard, structure of arrays: component chunk k of
 // site cb lives at p[k * stride + cb], so a wavefront's loads of one chunk
-// are contiguous.
+// are contiguous.  FP64 fields are instead tiled by 64 elements: component
+// k of element i lives at p[(i / 64 * 12 + k) * 64 + i % 64] (sp64_at), so a
+// wavefront's twelve loads of one spinor read one contiguous 12 KB run
+// rather than twelve runs a field apart (the stride, a multiple of 64, only
+// sizes the field).  The tile offset exceeds 32 bits on large fields, so
+// these accesses take a 64-bit lane address.
 struct SpF64 {   // 12 chunks of double2 (one complex each), 192 B / site
   double2* p;
   int stride;
 };
+__device__ __forceinline__ size_t sp64_at(int k, size_t i) { return (((i >> 6) * 12 + k) << 6) + (i & 63); }
 struct SpF32 {   // 6 chunks of float4 (two complex each), 96 B / site
   float4* p;
   int stride;
@@ -373,7 +379,7 @@ template <typename R>
 __device__ __forceinline__ void load(const SpF64& f, int i, Spinor<R>& v) {
 #pragma unroll
   for (int k = 0; k < 12; ++k) {
-    double2 d = *elem(f.p, (size_t)k * f.stride, i);
+    double2 d = f.p[sp64_at(k, i)];
     v.v[k / 3][k % 3] = {R(d.x), R(d.y)};
   }
 }
@@ -385,7 +391,7 @@ __device__ __forceinline__ void store(const SpF64& f, int i, const Spinor<R>& v)
 #pragma unroll
   for (int k = 0; k < 12; ++k) {
     const nt_d2 w = {double(v.v[k / 3][k % 3].re), double(v.v[k / 3][k % 3].im)};
-    __builtin_nontemporal_store(w, (nt_d2*)elem(f.p, (size_t)k * f.stride, i));
+    __builtin_nontemporal_store(w, (nt_d2*)(f.p + sp64_at(k, i)));
   }
 }
 // Site-local spinor read once per kernel (the k2 site term, the epilogue's y).
@@ -393,7 +399,7 @@ template <typename R>
 __device__ __forceinline__ void load_once(const SpF64& f, int i, Spinor<R>& v) {
 #pragma unroll
   for (int k = 0; k < 12; ++k) {
-    const double2 d = ld_stream(elem(f.p, (size_t)k * f.stride, i));
+    const double2 d = ld_stream(f.p + sp64_at(k, i));
     v.v[k / 3][k % 3] = {R(d.x), R(d.y)};
   }
 }

@@ -56,7 +56,7 @@ def test_noalloc_gauge_force_matches_allocating_entry_point():
 
 
 def test_noalloc_gauge_force_rejects_what_it_cannot_hold():
-    dims = (16, 16, 16, 32)  # 131072 sites: beyond the 116508 the fixed array holds
+    dims = (16, 16, 16, 32)  # 131072 sites: beyond the 116480 the fixed array holds
     lat = Lattice(dims, 0.125, 1.0)
     lat.load_gauge(to_dev(synth.unit_gauge(dims)), build_clover=False)
     g, f = _nan_buffers(lat.V)
