@@ -128,7 +128,9 @@ int qcd_version(void);
 
 /* Create a context for one lattice on HIP device `device`; all work goes to
  * `hip_stream` (a hipStream_t cast to uintptr_t; 0 = the null stream).
- * dims: {Lx, Ly, Lz, Lt}, each even and >= 2, V < 2^31.
+ * dims: {Lx, Ly, Lz, Lt}, each even and >= 2, V / 2 (rounded up to a multiple
+ * of 64) x 48 < 2^32, i.e. V up to about 1.79e8 (the kernels address a field
+ * element with a 32-bit byte offset).
  * Defaults: kappa = 0.125, c_sw = 1, t_boundary = -1.  Returns QCD_EINVAL on
  * a bad shape, QCD_ENOMEM / QCD_EHIP if the device work buffers cannot be made. */
 int qcd_create(const int dims[4], int device, uintptr_t hip_stream, qcd_ctx **out);
@@ -222,8 +224,8 @@ int qcd_solve(qcd_ctx *ctx, const qcd_solver_params *params, const void *b_dev, 
  * n_rhs.  The first call with a given n_rhs allocates the interleaved work
  * vectors (about 12 x n_rhs' spinor fields, n_rhs' = the rounded count); they
  * are kept for later calls with as many or fewer right-hand sides.
- * QCD_EINVAL if V/2 x n_rhs' reaches 2^28 (the kernels address a field
- * chunk with a 32-bit byte offset).  QCD_ENOCONV if any right-hand side
+ * QCD_EINVAL if V/2 (rounded up to a multiple of 64) x n_rhs' x 48 reaches
+ * 2^32 (the kernels address a field element with a 32-bit byte offset).  QCD_ENOCONV if any right-hand side
  * missed tol (all x are written). */
 int qcd_solve_multi(qcd_ctx *ctx, const qcd_solver_params *params, int n_rhs, const void *b_dev, void *x_dev,
                     qcd_solver_stats *stats);

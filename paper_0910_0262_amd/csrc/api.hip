@@ -839,7 +839,10 @@ int validate_dims(const int dims[4]) {
       return fail(QCD_EINVAL, "every lattice extent must be even and >= 2 (got " + std::to_string(dims[k]) + ")");
     v *= dims[k];
   }
-  if (v >= (1LL << 31) / 4) return fail(QCD_EINVAL, "lattice volume too large");
+  // a binary16 spinor element i is addressed with the 32-bit byte offset 48 i
+  // (64-element tiles of three 16-byte chunks): V / 2 * 48 < 2^32
+  if (v >= (1LL << 31) / 4 || (((v / 2 + 63) & ~63LL) * 48) >= (1LL << 32))
+    return fail(QCD_EINVAL, "lattice volume too large");
   return QCD_OK;
 }
 
@@ -1104,8 +1107,9 @@ struct WorkGuard {
 
 // Make the multi-source work set hold 1 << lg right-hand sides.
 int use_multi(qcd_ctx* c, int lg) {
-  // the stencil addresses a chunk element with a 32-bit byte offset (16-byte elements)
-  if (((long long)c->g.stride << lg) >= (1LL << 28))
+  // the stencils address a chunk element with a 32-bit byte offset (16-byte
+  // elements; 48 bytes per element of the tiled binary16 fields)
+  if (((long long)c->g.stride << lg) * 48 >= (1LL << 32))
     return fail(QCD_EINVAL, "too many interleaved right-hand sides for this lattice volume");
   if (c->wm.st == nullptr || c->wm_lg_alloc < lg) {
     free_work(c->wm);

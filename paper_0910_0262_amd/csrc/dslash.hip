@@ -310,8 +310,8 @@ __device__ __forceinline__ void load_half(const SpF64& f, int i, Cx<R> v[6]) {
 template <int H, typename R>
 __device__ __forceinline__ void load_half(const SpH& f, int i, Cx<R> v[6]) {
   const float s = *elem(f.s, 0, i);
-  const h4_t m = as_h4(((const uint2*)elem(f.p, (size_t)f.stride, i))[H]);
-  const h8_t o = as_h8(*elem(f.p, (size_t)(2 * H) * f.stride, i));
+  const h4_t m = as_h4(((const uint2*)elem(f.p, (size_t)64, sph_at(i)))[H]);
+  const h8_t o = as_h8(*elem(f.p, (size_t)(2 * H) * 64, sph_at(i)));
 #pragma unroll
   for (int j = 0; j < 4; ++j) v[H == 0 ? j : j + 2] = {R(float(o[2 * j]) * s), R(float(o[2 * j + 1]) * s)};
 #pragma unroll
@@ -354,8 +354,8 @@ __device__ __forceinline__ void store_half(const SpH& f, int i, const Cx<R> v[6]
   const uint2 wq = from_h4(q);
   const nt_u4 no = {wo.x, wo.y, wo.z, wo.w};
   const nt_u2 nq = {wq.x, wq.y};
-  __builtin_nontemporal_store(no, (nt_u4*)elem(f.p, (size_t)(2 * H) * f.stride, i));
-  __builtin_nontemporal_store(nq, (nt_u2*)elem(f.p, (size_t)f.stride, i) + H);
+  __builtin_nontemporal_store(no, (nt_u4*)elem(f.p, (size_t)(2 * H) * 64, sph_at(i)));
+  __builtin_nontemporal_store(nq, (nt_u2*)elem(f.p, (size_t)64, sph_at(i)) + H);
   if (H == 1) __builtin_nontemporal_store(m, elem(f.s, 0, i));
 }
 

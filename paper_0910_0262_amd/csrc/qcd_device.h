@@ -365,6 +365,10 @@ struct SpF64 {   // 12 chunks of double2 (one complex each), 192 B / site
   int stride;
 };
 __device__ __forceinline__ size_t sp64_at(int k, size_t i) { return (((i >> 6) * 12 + k) << 6) + (i & 63); }
+// binary16 fields are tiled the same way: 16-byte chunk k of element i at
+// p[(i / 64 * 3 + k) * 64 + i % 64]; chunk k is then element sph_at(i) of
+// chunk-base p + 64 k, a 32-bit index (the host keeps 48 i below 2^32).
+__device__ __forceinline__ int sph_at(int i) { return ((i >> 6) * 3 << 6) + (i & 63); }
 struct SpF32 {   // 6 chunks of float4 (two complex each), 96 B / site
   float4* p;
   int stride;
@@ -439,7 +443,7 @@ template <typename R>
 __device__ __forceinline__ void load_raw(const SpH& f, int i, Spinor<R>& v) {
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    h8_t h = as_h8(*elem(f.p, (size_t)k * f.stride, i));
+    h8_t h = as_h8(*elem(f.p, (size_t)k * 64, sph_at(i)));
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int c = 4 * k + j;
@@ -455,7 +459,7 @@ __device__ __forceinline__ void load(const SpH& f, int i, Spinor<R>& v) {
   const float s = *elem(f.s, 0, i);
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    h8_t h = as_h8(*elem(f.p, (size_t)k * f.stride, i));
+    h8_t h = as_h8(*elem(f.p, (size_t)k * 64, sph_at(i)));
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int c = 4 * k + j;  // complex component 0..11
@@ -493,7 +497,7 @@ __device__ __forceinline__ void store(const SpH& f, int i, const Spinor<R>& v) {
   for (int k = 0; k < 3; ++k) {
     const uint4 w = from_h8(h[k]);
     const nt_u4 q = {w.x, w.y, w.z, w.w};
-    __builtin_nontemporal_store(q, (nt_u4*)elem(f.p, (size_t)k * f.stride, i));
+    __builtin_nontemporal_store(q, (nt_u4*)elem(f.p, (size_t)k * 64, sph_at(i)));
   }
   __builtin_nontemporal_store(m, elem(f.s, 0, i));
 }

@@ -69,6 +69,21 @@ def test_create_rejects_bad_shapes(dims):
     assert "even" in capi.last_error()
 
 
+@pytest.mark.parametrize("dims", [(64, 64, 64, 684), (2, 2, 2, 1 << 28)])
+def test_create_rejects_too_large_volume(dims):
+    """V/2 (rounded up to a multiple of 64) x 48 must stay below 2^32 (the
+    kernels address a binary16 spinor element with a 32-bit byte offset):
+    64^3 x 684 is just past that bound; rejected before any device call."""
+    vh = (dims[0] * dims[1] * dims[2] * dims[3] // 2 + 63) // 64 * 64
+    assert vh * 48 >= 1 << 32
+    lib = capi.lib()
+    out = ctypes.c_void_p(123)
+    d = (ctypes.c_int * 4)(*dims)
+    assert lib.qcd_create(d, 0, 0, ctypes.byref(out)) == capi.QCD_EINVAL
+    assert out.value is None
+    assert "too large" in capi.last_error()
+
+
 def test_null_arguments_are_rejected():
     lib = capi.lib()
     d = (ctypes.c_int * 4)(4, 4, 4, 4)
