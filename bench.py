@@ -41,14 +41,18 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 # compiled with them disabled): 256 CUs x 64 lanes x 2 flops x 2.4 GHz
 FP32_VALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
 FLOPS_PER_SITE = 1824.0  # 1320 hopping + 504 clover per site per M application
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_dslash_mixed_32x32x32x64.md")
-# kernels whose HBM traffic the committed counter summary records: the mixed
-# k2 and k1 launches of the multi-source solve (the timed headline) and the
-# mixed k1 of the single-source solve
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_dslash_32x32x32x64.md")
+# kernels whose HBM traffic the committed counter summary records: the k2 and
+# k1 launches of the multi-source solves (mixed: the timed headline; FP64:
+# its reliable updates and the FP64 solve) and of the single-source ones
 TRAFFIC_KERNELS = {
     "k2_mixed_multi": ("dslash_kernel<float, 2, false, false, true,", "LinkH18, qcd::CloverHC,"),
     "k1_mixed_multi": ("dslash_kernel<float, 0, true, false, true,", "LinkH18", "CloverH>"),
     "k1_mixed_single": ("dslash_kernel<float, 0, true, false, false,", "LinkH12", "CloverH>"),
+    "k2_fp64_multi": ("dslash_kernel<double, 2, false, false, true,", "qcd::CloverF64C, qcd::CloverNone>"),
+    "k1_fp64_multi": ("dslash_kernel<double, 0, true, false, true,", "qcd::CloverNone, qcd::CloverF64>"),
+    "k2_fp64_single": ("dslash_kernel<double, 2, false, false, false,", "qcd::CloverF64C, qcd::CloverNone>"),
+    "k1_fp64_single": ("dslash_kernel<double, 0, true, false, false,", "qcd::CloverNone, qcd::CloverF64>"),
 }
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_0910_0262_amd", "csrc", f) for f in ("qcd_device.h", "qcd_internal.h", "dslash.hip")]
 
@@ -152,7 +156,9 @@ def traffic_summary(fetch_csv: str, write_csv: str, vh: int, command: str, nr: i
     copy_bytes = float(2 << 30)
     fs, ws = copy_bytes / (f_c * 1024.0), copy_bytes / (w_c * 1024.0)
     alg = {"k2_mixed_multi": k2_bytes_multi("mixed", nr) * vh, "k1_mixed_multi": k1_bytes_multi("mixed", nr) * vh,
-           "k1_mixed_single": k1_bytes_per_site("mixed") * vh}
+           "k1_mixed_single": k1_bytes_per_site("mixed") * vh,
+           "k2_fp64_multi": k2_bytes_multi("fp64", nr) * vh, "k1_fp64_multi": k1_bytes_multi("fp64", nr) * vh,
+           "k2_fp64_single": k2_bytes_per_site("fp64") * vh, "k1_fp64_single": k1_bytes_per_site("fp64") * vh}
     kernels = {}
     for key, tokens in TRAFFIC_KERNELS.items():
         f_k, n_f = mean_of(fr, tokens)
@@ -164,7 +170,7 @@ def traffic_summary(fetch_csv: str, write_csv: str, vh: int, command: str, nr: i
     rec = {"vh": vh, "nr_multi": nr, "copy_fetch_kib": f_c, "copy_write_kib": w_c, "copy_bytes": copy_bytes,
            "fetch_scale": fs, "write_scale": ws, "kernels": kernels, "source_sha256": kernel_source_hash()}
     with open(TRAFFIC_FILE, "w") as f:
-        f.write("# HBM traffic of the mixed stencils at 32x32x32x64 (rocprofv3 counters)\n\n")
+        f.write("# HBM traffic of the stencils at 32x32x32x64 (rocprofv3 counters)\n\n")
         f.write("Two counter passes over the same command, run from the repository root on one MI355X:\n\n")
         f.write("```\n" + command + "\n```\n\n")
         f.write(f"FETCH_SIZE reads {f_c:.0f} KiB and WRITE_SIZE {w_c:.0f} KiB per dispatch of the 2 GiB copy "
