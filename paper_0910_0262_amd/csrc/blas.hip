@@ -19,8 +19,11 @@ __global__ void pack_spinor_full_k(Geom g, const double2* __restrict__ user, SpF
   lex_coords(i, g, x);
   const SpF64 f = parity_of(x) ? o : e;
   const int cb = i >> 1;
+  double2 v[12];
 #pragma unroll
-  for (int k = 0; k < 12; ++k) f.p[sp64_at(k, cb)] = user[(size_t)i * 12 + k];
+  for (int k = 0; k < 12; ++k) v[k] = user[(size_t)i * 12 + k];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) f.p[sp64_at(k, cb)] = v[k];
 }
 __global__ void unpack_spinor_full_k(Geom g, SpF64 e, SpF64 o, double2* __restrict__ user) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -29,20 +32,29 @@ __global__ void unpack_spinor_full_k(Geom g, SpF64 e, SpF64 o, double2* __restri
   lex_coords(i, g, x);
   const SpF64 f = parity_of(x) ? o : e;
   const int cb = i >> 1;
+  double2 v[12];
 #pragma unroll
-  for (int k = 0; k < 12; ++k) user[(size_t)i * 12 + k] = f.p[sp64_at(k, cb)];
+  for (int k = 0; k < 12; ++k) v[k] = f.p[sp64_at(k, cb)];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) user[(size_t)i * 12 + k] = v[k];
 }
 __global__ void pack_spinor_cb_k(int n, const double2* __restrict__ user, SpF64 f) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  double2 v[12];
 #pragma unroll
-  for (int k = 0; k < 12; ++k) f.p[sp64_at(k, i)] = user[(size_t)i * 12 + k];
+  for (int k = 0; k < 12; ++k) v[k] = user[(size_t)i * 12 + k];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) f.p[sp64_at(k, i)] = v[k];
 }
 __global__ void unpack_spinor_cb_k(int n, SpF64 f, double2* __restrict__ user) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  double2 v[12];
 #pragma unroll
-  for (int k = 0; k < 12; ++k) user[(size_t)i * 12 + k] = f.p[sp64_at(k, i)];
+  for (int k = 0; k < 12; ++k) v[k] = f.p[sp64_at(k, i)];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) user[(size_t)i * 12 + k] = v[k];
 }
 
 // n right-hand sides [n][V][12] -> interleaved fields, element (cb << lg) | r;
@@ -55,9 +67,11 @@ __global__ void pack_spinor_multi_k(Geom g, int lg, int n, const double2* __rest
   lex_coords(i, g, x);
   const SpF64 f = parity_of(x) ? o : e;
   const size_t v = ((size_t)(i >> 1) << lg) | r;
+  double2 w[12];
 #pragma unroll
-  for (int k = 0; k < 12; ++k)
-    f.p[sp64_at(k, v)] = r < n ? user[((size_t)r * g.V + i) * 12 + k] : make_double2(0.0, 0.0);
+  for (int k = 0; k < 12; ++k) w[k] = r < n ? user[((size_t)r * g.V + i) * 12 + k] : make_double2(0.0, 0.0);
+#pragma unroll
+  for (int k = 0; k < 12; ++k) f.p[sp64_at(k, v)] = w[k];
 }
 __global__ void unpack_spinor_multi_k(Geom g, int lg, int n, SpF64 e, SpF64 o, double2* __restrict__ user) {
   const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -68,8 +82,11 @@ __global__ void unpack_spinor_multi_k(Geom g, int lg, int n, SpF64 e, SpF64 o, d
   lex_coords(i, g, x);
   const SpF64 f = parity_of(x) ? o : e;
   const size_t v = ((size_t)(i >> 1) << lg) | r;
+  double2 w[12];
 #pragma unroll
-  for (int k = 0; k < 12; ++k) user[((size_t)r * g.V + i) * 12 + k] = f.p[sp64_at(k, v)];
+  for (int k = 0; k < 12; ++k) w[k] = f.p[sp64_at(k, v)];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) user[((size_t)r * g.V + i) * 12 + k] = w[k];
 }
 hipError_t launch_pack_spinor_multi(const Geom& g, int lg, int n, const double2* user, SpF64 e, SpF64 o,
                                     hipStream_t s) {
@@ -435,26 +452,40 @@ __global__ void __launch_bounds__(256) xp_update_f64_k(Geom g, int lg, const CgS
   double a[NOLD + 1];
 #pragma unroll
   for (int m = 0; m <= NOLD; ++m) a[m] = st->ah[m];
+  // six components at a time, every load of them issued before their stores
+  // (the compiler cannot tell the fields apart, so a store would hold back
+  // the loads after it: one memory round trip per component instead of two
+  // per site, which small lattices cannot hide)
 #pragma unroll
-  for (int k = 0; k < 12; ++k) {
-    const size_t o = sp64_at(k, i);
-    const double2 pv = pc.p[o];
+  for (int hh = 0; hh < 2; ++hh) {
+    double2 pv[6], rv[6], xv[6], acc[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) pv[k] = pc.p[sp64_at(6 * hh + k, i)];
+    if (dp) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) rv[k] = r.p[sp64_at(6 * hh + k, i)];
+    }
     if (dx) {
-      double2 acc = make_double2(a[0] * pv.x, a[0] * pv.y);
 #pragma unroll
-      for (int m = 1; m <= NOLD; ++m) {
-        const double2 q = old.p[m - 1].p[o];
-        acc.x += a[m] * q.x;
-        acc.y += a[m] * q.y;
+      for (int k = 0; k < 6; ++k) {
+        xv[k] = x.p[sp64_at(6 * hh + k, i)];
+        acc[k] = make_double2(a[0] * pv[k].x, a[0] * pv[k].y);
       }
-      double2 xv = x.p[o];
-      xv.x += acc.x;
-      xv.y += acc.y;
-      x.p[o] = xv;
+#pragma unroll
+      for (int m = 1; m <= NOLD; ++m)
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+          const double2 q = old.p[m - 1].p[sp64_at(6 * hh + k, i)];
+          acc[k].x += a[m] * q.x;
+          acc[k].y += a[m] * q.y;
+        }
+#pragma unroll
+      for (int k = 0; k < 6; ++k) x.p[sp64_at(6 * hh + k, i)] = make_double2(xv[k].x + acc[k].x, xv[k].y + acc[k].y);
     }
     if (dp) {
-      const double2 rv = r.p[o];
-      pout.p[o] = make_double2(rv.x + be * pv.x, rv.y + be * pv.y);
+#pragma unroll
+      for (int k = 0; k < 6; ++k)
+        pout.p[sp64_at(6 * hh + k, i)] = make_double2(rv[k].x + be * pv[k].x, rv[k].y + be * pv[k].y);
     }
   }
 }
@@ -464,11 +495,9 @@ __global__ void __launch_bounds__(256) p_restart_f64_k(Geom g, int lg, const CgS
   st += i & ((1 << lg) - 1);
   if (!st->do_p) return;
   if (i >= g.Vh) return;
-#pragma unroll
-  for (int k = 0; k < 12; ++k) {
-    const size_t o = sp64_at(k, i);
-    p.p[o] = r.p[o];
-  }
+  Spinor<double> v;
+  load(r, i, v);
+  store(p, i, v);
 }
 // mixed: the same cycle with x in FP32 and the directions in binary16
 // (re-encoded per site when written).
