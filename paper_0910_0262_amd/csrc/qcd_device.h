@@ -352,22 +352,23 @@ __device__ __forceinline__ uint4 ld_stream(const uint4* p) {
 __device__ __forceinline__ unsigned int ld_stream(const unsigned int* p) { return __builtin_nontemporal_load(p); }
 
 // ------------------------------------------------------------------ spinor fields
-// Each field is one checkerboard, structure of arrays: component chunk k of
-// site cb lives at p[k * stride + cb], so a wavefront's loads of one chunk
-// are contiguous.  FP64 fields are instead tiled by 64 elements: component
-// k of element i lives at p[(i / 64 * 12 + k) * 64 + i % 64] (sp64_at), so a
-// wavefront's twelve loads of one spinor read one contiguous 12 KB run
-// rather than twelve runs a field apart (the stride, a multiple of 64, only
-// sizes the field).  The tile offset exceeds 32 bits on large fields, so
-// these accesses take a 64-bit lane address.
+// Each field is one checkerboard.  The FP64 and binary16 spinors are stored
+// in tiles of 64 elements with the chunks of a tile contiguous: chunk k of
+// element i at p[(i / 64 * nchunks + k) * 64 + i % 64] (sp64_at, sph_at), so
+// a wavefront's loads of one spinor read one contiguous run (12 KB, 3 KB)
+// rather than one run per chunk a field apart; the stride, a multiple of 64,
+// only sizes the field.  The FP32 x accumulator is plain structure of
+// arrays, chunk k of element i at p[k * stride + i].  The FP64 tile offset
+// exceeds 32 bits on large fields, so those accesses take a 64-bit lane
+// address.
 struct SpF64 {   // 12 chunks of double2 (one complex each), 192 B / site
   double2* p;
   int stride;
 };
 __device__ __forceinline__ size_t sp64_at(int k, size_t i) { return (((i >> 6) * 12 + k) << 6) + (i & 63); }
-// binary16 fields are tiled the same way: 16-byte chunk k of element i at
-// p[(i / 64 * 3 + k) * 64 + i % 64]; chunk k is then element sph_at(i) of
-// chunk-base p + 64 k, a 32-bit index (the host keeps 48 i below 2^32).
+// binary16: 16-byte chunk k of element i is element sph_at(i) counted from
+// p + 64 k, a 32-bit index (the host keeps 48 i below 2^32); the per-site
+// scales are a plain array.
 __device__ __forceinline__ int sph_at(int i) { return ((i >> 6) * 3 << 6) + (i & 63); }
 struct SpF32 {   // 6 chunks of float4 (two complex each), 96 B / site
   float4* p;
