@@ -667,7 +667,7 @@ double xp_bytes_per_iter(const qcd_ctx* c, bool mixed) {
 }
 
 // FP64 CG on Mhat^dag Mhat x = rhs (V_RHS) into V_X, from x = 0 or (use_x0) from V_X.
-// Work slots: V_R, V_P, V_Q, V_T.
+// Work slots: V_R, V_Q, V_T and the x cycle's directions V_P, V_P1 .. V_P3.
 int cg_fp64(qcd_ctx* c, const qcd_solver_params* p, bool use_x0, CgCounters& cnt) {
   const Geom& g = c->g;
   const int B = c->block();
