@@ -94,9 +94,10 @@ typedef enum {
                                replay measured no faster on MI355X)                     */
   QCD_OPT_SMALL_GRID = 4,   /* single-source stencils on lattices of at most 2^17 sites
                                (fewer sites per checkerboard than SIMD lanes on the
-                               chip), with 64-thread workgroups: 1 (default) = two
-                               wavefronts per 64 sites (forward and backward hops split,
-                               partial sums exchanged in LDS), 0 = one work-item per
+                               chip), with 64-thread workgroups: 2 (default) = four
+                               wavefronts per 64 sites (one direction each, partial
+                               sums added in LDS), 1 = two wavefronts per 64 sites
+                               (forward and backward hops split), 0 = one work-item per
                                site as on large lattices                                */
   QCD_OPT_MIXED_STALL = 5,  /* mixed CG fallback threshold k in [1, 60], default 1: the
                                FP64 |r|^2 recomputed at a reliable update must fall

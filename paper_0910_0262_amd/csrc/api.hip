@@ -89,7 +89,7 @@ struct qcd_ctx {
   int link_recon = 12;
   int mixed_clover = 16;
   int use_graph = 0;
-  int small_grid = 1;
+  int small_grid = 2;
   int block_opt = 0;
   int stall_log2 = 1;  // mixed CG: a reliable update must take |r|^2 below 2^-stall_log2 of its best
   int x_defer = 4;     // CG: iterations per x update (QCD_OPT_X_CYCLE)
@@ -962,7 +962,7 @@ int qcd_set_option(qcd_ctx* c, int option, int value) {
       c->use_graph = value;
       return QCD_OK;
     case QCD_OPT_SMALL_GRID:
-      if (value != 0 && value != 1) return fail(QCD_EINVAL, "small-grid option must be 0 or 1");
+      if (value < 0 || value > 2) return fail(QCD_EINVAL, "small-grid option must be 0, 1 or 2");
       c->small_grid = value;
       return QCD_OK;
     case QCD_OPT_COMPACT_CLOVER:

@@ -440,13 +440,12 @@ __device__ __forceinline__ void pair_hops(const A& a, int i, int lane, PairLds<R
   }
 }
 
-// Phase 2 of wavefront H: the whole half, hop factor, site term, clover, epilogue value.
+// Chiral half H of a site from the sum v of all its hops: hop factor, site
+// term, clover, epilogue value; returns the half's max |component|.
 template <int H, typename R, int SITE, bool POST, class A>
-__device__ __forceinline__ void pair_finish(const A& a, int i, int lane, PairLds<R>& L, Cx<R> v[6]) {
+__device__ __forceinline__ float finish_half(const A& a, int i, Cx<R> v[6]) {
   const R c = H == 0 ? R(a.c) : (a.g5out ? R(-a.c) : R(a.c));
   constexpr bool FUSED_CL = sizeof(R) == 4;
-#pragma unroll
-  for (int j = 0; j < 6; ++j) v[j] = v[j] + L.part[H][j][lane];
   if constexpr (POST && SITE == 0) {
     apply_block<H, FUSED_CL>(a.cpost, i, v, c);
   } else {
@@ -481,7 +480,16 @@ __device__ __forceinline__ void pair_finish(const A& a, int i, int lane, PairLds
 #pragma unroll
     for (int j = 0; j < 6; ++j) v[j] = yv[j] + al * v[j];
   }
-  L.m[H][lane] = half_max(v);
+  return half_max(v);
+}
+
+// Phase 2 of wavefront H: the whole half (its own hops and the other
+// wavefront's), then finish_half.
+template <int H, typename R, int SITE, bool POST, class A>
+__device__ __forceinline__ void pair_finish(const A& a, int i, int lane, PairLds<R>& L, Cx<R> v[6]) {
+#pragma unroll
+  for (int j = 0; j < 6; ++j) v[j] = v[j] + L.part[H][j][lane];
+  L.m[H][lane] = finish_half<H, R, SITE, POST>(a, i, v);
 }
 
 template <typename R, int SITE, bool POST, bool G5IN, class A>
@@ -516,6 +524,83 @@ __global__ void __launch_bounds__(128) dslash_pair_kernel(A a) {
   if (live) {
     const float m = fmaxf(L.m[0][lane], L.m[1][lane]);
     if (h == 0)
+      store_half<0>(a.out, i, v, m);
+    else
+      store_half<1>(a.out, i, v, m);
+    if (a.epi >= 1) {
+#pragma unroll
+      for (int j = 0; j < 6; ++j) nrm += double(v[j].re) * double(v[j].re) + double(v[j].im) * double(v[j].im);
+    }
+  }
+  if (a.epi >= 1) block_sum_store(nrm, a.partial, blk);
+}
+
+// ------------------------------------------------------------------ small grids: four wavefronts per 64 sites
+// (small-grid option 2) Wavefront mu of a workgroup of four takes both hops
+// of direction mu for the 64 sites; the four partial sums meet in LDS, and
+// wavefronts 0 and 1 add them (in the order of the wavefronts) for chiral
+// halves 0 and 1 and finish those as in the two-wavefront form.  Each
+// wavefront waits out two hops instead of four, and twice as many are in
+// flight.
+template <typename R>
+struct QuadLds {
+  Cx<R> part[4][2][6][64];  // [wavefront][half][component][site]
+  float m[2][64];           // per-half max |component| of a binary16 output
+};
+
+template <int MU, typename R, bool G5IN, class A>
+__device__ __forceinline__ void quad_hops(const A& a, int i, Spinor<R>& acc) {
+  int x[4];
+  cb_coords(i, a.par_out, a.g, x);
+  zero(acc);
+  hop_one<MU, -1, G5IN, true>(a, i, x, acc);
+  hop_one<MU, +1, G5IN, true>(a, i, x, acc);
+}
+
+template <typename R, int SITE, bool POST, bool G5IN, class A>
+__global__ void __launch_bounds__(256) dslash_quad_kernel(A a) {
+  // as in dslash_kernel: a launch that finishes alpha never reads halt, so
+  // all four wavefronts of every workgroup reach the barriers below
+  if (a.fin_nr > 0)
+    fused_fin_alpha(a);
+  else if (a.st != nullptr && a.st->halt)
+    return;
+  __shared__ QuadLds<R> L;
+  const int blk = xcd_block(blockIdx.x, gridDim.x);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int i = blk * 64 + lane;
+  const bool live = i < a.g.Vh;
+  if (live) {
+    Spinor<R> acc;
+    if (w == 0)
+      quad_hops<0, R, G5IN>(a, i, acc);
+    else if (w == 1)
+      quad_hops<1, R, G5IN>(a, i, acc);
+    else if (w == 2)
+      quad_hops<2, R, G5IN>(a, i, acc);
+    else
+      quad_hops<3, R, G5IN>(a, i, acc);
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int j = 0; j < 6; ++j) L.part[w][h][j][lane] = acc.v[2 * h + j / 3][j % 3];
+  }
+  __syncthreads();
+  Cx<R> v[6];
+  if (live && w < 2) {
+#pragma unroll
+    for (int j = 0; j < 6; ++j)
+      v[j] = ((L.part[0][w][j][lane] + L.part[1][w][j][lane]) + L.part[2][w][j][lane]) + L.part[3][w][j][lane];
+    if (w == 0)
+      L.m[0][lane] = finish_half<0, R, SITE, POST>(a, i, v);
+    else
+      L.m[1][lane] = finish_half<1, R, SITE, POST>(a, i, v);
+  }
+  __syncthreads();
+  double nrm = 0.0;
+  if (live && w < 2) {
+    const float m = fmaxf(L.m[0][lane], L.m[1][lane]);
+    if (w == 0)
       store_half<0>(a.out, i, v, m);
     else
       store_half<1>(a.out, i, v, m);
@@ -617,6 +702,8 @@ static hipError_t run_g5(const Geom& g, const DslashOp& op, int block, hipStream
     return hipErrorInvalidValue;
   else if (g.Vh <= kSmallVh && op.small_grid == 1 && block == 64)
     hipLaunchKernelGGL((dslash_pair_kernel<R, SITE, POST, G5IN, decltype(a)>), dim3(nb), dim3(128), 0, s, a);
+  else if (g.Vh <= kSmallVh && op.small_grid == 2 && block == 64)
+    hipLaunchKernelGGL((dslash_quad_kernel<R, SITE, POST, G5IN, decltype(a)>), dim3(nb), dim3(256), 0, s, a);
   else
     hipLaunchKernelGGL((dslash_kernel<R, SITE, POST, G5IN, false, decltype(a)>), dim3(nb), dim3(block), 0, s, a);
   return hipGetLastError();

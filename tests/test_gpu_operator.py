@@ -173,10 +173,10 @@ def test_eclover_on_loaded_indefinite_block():
     lat.close()
 
 
-@pytest.mark.parametrize("small_grid", [0, 1])
+@pytest.mark.parametrize("small_grid", [0, 1, 2])
 def test_small_grid_forms(case, small_grid):
     """The single-source stencil forms a small lattice can take (one work-item
-    per site, two wavefronts per 64 sites) each give the oracle's operators:
+    per site, two or four wavefronts per 64 sites) each give the oracle's operators:
     FP64 to rounding, mixed within the binary16 storage error; their solves
     (norm and update epilogues) agree with the default form's to within
     cond * tol."""
@@ -189,13 +189,14 @@ def test_small_grid_forms(case, small_grid):
         assert rel_err(lat.apply(op, to_dev(psi), prec="mixed"), fn(e)) < 5e-3, op
     b = to_dev(synth.gaussian_source(dims, 16, 0))
     xs = {prec: lat.solve(b, prec=prec, tol=1e-12)[0] for prec in ("fp64", "mixed")}
-    lat.set_option(capi.QCD_OPT_SMALL_GRID, 1)
+    lat.set_option(capi.QCD_OPT_SMALL_GRID, 2)
     for prec in ("fp64", "mixed"):
         x1, st = lat.solve(b, prec=prec, tol=1e-12)
         assert rel_err(xs[prec], x1) < 1e-9, prec
         assert st["true_rel_res"] < 1e-10
-    with pytest.raises(QCDError, match="EINVAL"):
-        lat.set_option(capi.QCD_OPT_SMALL_GRID, 2)
+    for bad in (-1, 3):
+        with pytest.raises(QCDError, match="EINVAL"):
+            lat.set_option(capi.QCD_OPT_SMALL_GRID, bad)
 
 
 def test_encode_half_bit_exact(case):
