@@ -137,7 +137,7 @@ struct DslashOp {
   // and the partial sums of right-hand side r start at partial[r * blocks].
   int lg;
   // single-source kernel on small lattices: 0 one work-item per site, 1 two
-  // wavefronts per 64 sites
+  // wavefronts per 64 sites, 2 four
   int small_grid;
   // fin_nr > 0: before its stencil work, workgroup r < fin_nr of the launch
   // finishes alpha for right-hand side r, exactly as the finalisation kernel
