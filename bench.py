@@ -171,7 +171,8 @@ def traffic_summary(fetch_csv: str, write_csv: str, vh: int, command: str, nr: i
            "fetch_scale": fs, "write_scale": ws, "kernels": kernels, "source_sha256": kernel_source_hash()}
     with open(TRAFFIC_FILE, "w") as f:
         f.write("# HBM traffic of the stencils at 32x32x32x64 (rocprofv3 counters)\n\n")
-        f.write("Two counter passes over the same command, run from the repository root on one MI355X:\n\n")
+        f.write("Two counter passes (FETCH_SIZE, then WRITE_SIZE) over the same program, run from the repository "
+                "root on one MI355X:\n\n")
         f.write("```\n" + command + "\n```\n\n")
         f.write(f"FETCH_SIZE reads {f_c:.0f} KiB and WRITE_SIZE {w_c:.0f} KiB per dispatch of the 2 GiB copy "
                 f"kernel, so they are scaled by {fs:.3f} and {ws:.3f}.\n\n")
@@ -383,6 +384,8 @@ def main() -> int:
     ap.add_argument("--traffic-command", type=str, default="")
     args = ap.parse_args()
     if args.traffic_summary:
+        if not args.traffic_command.strip():
+            ap.error("--traffic-summary needs --traffic-command: the rocprofv3 commands the CSVs came from")
         d = tuple(int(v) for v in args.dims.split(","))
         traffic_summary(args.traffic_summary[0], args.traffic_summary[1], d[0] * d[1] * d[2] * d[3] // 2,
                         args.traffic_command)
