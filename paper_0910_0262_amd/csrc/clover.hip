@@ -9,7 +9,7 @@
 //   upper: X = F03 - F12, Y = F02 + F13, Z = F23 - F01
 //   lower: X = -F12 - F03, Y = F02 - F13, Z = -F01 - F23,
 // and s1 (x) X + s2 (x) Y + s3 (x) Z = [[Z, X - iY], [X + iY, -Z]].
-#include "qcd_internal.h"
+#include "md_order.h"
 
 namespace qcd {
 
@@ -73,10 +73,10 @@ __device__ Mat<double> field_strength(const double2* u18, const Geom& g, const i
 
 __global__ void __launch_bounds__(64) clover_build_k(Geom g, const double2* __restrict__ u18, double kc,
                                                      double2* __restrict__ clov) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= g.V) return;
+  const int j = md_position();
+  if (j >= g.V) return;
   int x[4];
-  lex_coords(i, g, x);
+  const int i = md_site(j, g, x);
   const int par = parity_of(x), cb = i >> 1;
   const Mat<double> f01 = field_strength(u18, g, x, 0, 1);
   const Mat<double> f02 = field_strength(u18, g, x, 0, 2);

@@ -19,7 +19,7 @@
 // of the traceless part of Gamma; each link enters the leaves of 6 plaquettes
 // at 4 corners each, and a leaf derivative is the product of the other three
 // links with Xi inserted at the leaf's corner.
-#include "qcd_internal.h"
+#include "md_order.h"
 
 namespace qcd {
 
@@ -93,10 +93,10 @@ __device__ __forceinline__ Mat<double> hop_force_dir(const Geom& g, const int x[
 
 __global__ void __launch_bounds__(128) force_hop_k(Geom g, const double2* __restrict__ u18, SpF64 le, SpF64 lo,
                                                    SpF64 re, SpF64 ro, double coef, double2* __restrict__ gint) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= g.V) return;
+  const int j = md_position();
+  if (j >= g.V) return;
   int x[4];
-  lex_coords(i, g, x);
+  const int i = md_site(j, g, x);
   const int par = parity_of(x), cb = i >> 1;
   Mat<double> f[4];
   f[0] = hop_force_dir<0>(g, x, le, lo, re, ro);
@@ -279,11 +279,8 @@ __device__ __forceinline__ Mat<double> insertion(F1 l1, F2 l2, F3 l3, G0 c0, G1 
 __global__ void __launch_bounds__(64) force_clover_k(Geom g, const double2* __restrict__ u18,
                                                      const double2* __restrict__ xi, double coef,
                                                      double2* __restrict__ gint) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= 4 * g.V) return;
-  const int mu = t / g.V, i = t - mu * g.V;
-  int y[4];
-  lex_coords(i, g, y);
+  int mu, i, y[4];
+  if (!md_link(g, mu, i, y)) return;
   const int par = parity_of(y), cb = i >> 1;
   Mat<double> mt = mzero<double>();
 #pragma unroll 1
@@ -334,7 +331,7 @@ __global__ void __launch_bounds__(64) force_clover_k(Geom g, const double2* __re
 
 hipError_t launch_force_clover(const Geom& g, const double2* u18, const double2* xi, double coef, double2* gint,
                                hipStream_t s) {
-  hipLaunchKernelGGL(force_clover_k, dim3(blocks_for(4 * g.V, 64)), dim3(64), 0, s, g, u18, xi, coef, gint);
+  hipLaunchKernelGGL(force_clover_k, dim3(md_link_blocks(g)), dim3(64), 0, s, g, u18, xi, coef, gint);
   return hipGetLastError();
 }
 
@@ -364,11 +361,8 @@ __device__ __forceinline__ Mat<double> staple_sum(const double2* u18, const Geom
 // gint(mu, x) (+)= coef A_mu(x)^dag; one thread per link.
 __global__ void __launch_bounds__(64) gauge_force_k(Geom g, const double2* __restrict__ u18, double coef,
                                                     int accumulate, double2* __restrict__ gint) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= 4 * g.V) return;
-  const int mu = t / g.V, i = t - mu * g.V;
-  int y[4];
-  lex_coords(i, g, y);
+  int mu, i, y[4];
+  if (!md_link(g, mu, i, y)) return;
   const int par = parity_of(y), cb = i >> 1;
   const Mat<double> a = staple_sum(u18, g, mu, y);
   double2* base = gint + (size_t)((mu * 2 + par) * 9) * g.stride;
@@ -382,7 +376,7 @@ __global__ void __launch_bounds__(64) gauge_force_k(Geom g, const double2* __res
 
 hipError_t launch_gauge_force(const Geom& g, const double2* u18, double coef, int accumulate, double2* gint,
                               hipStream_t s) {
-  hipLaunchKernelGGL(gauge_force_k, dim3(blocks_for(4 * g.V, 64)), dim3(64), 0, s, g, u18, coef, accumulate, gint);
+  hipLaunchKernelGGL(gauge_force_k, dim3(md_link_blocks(g)), dim3(64), 0, s, g, u18, coef, accumulate, gint);
   return hipGetLastError();
 }
 
