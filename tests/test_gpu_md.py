@@ -182,3 +182,56 @@ def test_trajectory_matches_hmd_steps():
     assert float(torch.abs(U1 - U2).max()) < 1e-13
     assert float(torch.abs(P1 - P2).max()) < 1e-10
     lat.close()
+
+
+# ---------------------------------------------------------------- full lattice, sampled
+def _block(u, off, n):
+    """The n^4 block of a (Lt, Lz, Ly, Lx, 4, 3, 3) field whose first site is off = (t, z, y, x),
+    taken periodically."""
+    idx = [(o + np.arange(n)) % ext for o, ext in zip(off, u.shape[:4])]
+    return u[np.ix_(*idx)], idx
+
+
+@pytest.fixture(scope="module")
+def full32():
+    dims = (32, 32, 32, 64)
+    print(f"[md full lattice dims={dims} width=0.2 kappa=0.1255 csw=1.0 seed=0]", flush=True)
+    u = synth.random_su3_field(dims, 0.2, 0)
+    lat = Lattice(dims, 0.1255, 1.0)
+    lat.load_gauge(to_dev(u))
+    yield u, lat
+    lat.close()
+
+
+@pytest.mark.parametrize("force", ["gauge", "det"])
+def test_md_forces_full_lattice_sampled(full32, force):
+    """32^3x64 with the headline input (width 0.2, kappa 0.1255, c_sw 1), in the
+    launch shape of an MD step there.  The gauge force on a link depends only on
+    the links within one site of it, the clover-determinant force on those within
+    two (through A at the neighbouring sites), so the oracle's force on an n^4
+    block cut out of the lattice (n = 4 and 6) is exact at the links whose block
+    coordinates all lie in [r, n - 1 - r] (r = 1 and 2): no plaquette or clover
+    leaf through them wraps around the block.  Blocks at several offsets, some
+    across the lattice's own periodic edges, each with an even coordinate sum so
+    that the block's odd sites are the lattice's odd sites."""
+    u, lat = full32
+    if force == "gauge":
+        S, G, _ = lat.gauge_action_force(BETA, want_F=False)
+        n, r, bar = 4, 1, 1e-12
+        fn = lambda v: md.gauge_action(v, BETA)  # noqa: E731
+    else:
+        S, G, _ = lat.clover_det_action_force(want_F=False)
+        n, r, bar = 6, 2, 1e-11
+        fn = lambda v: md.clover_det_action(v, 0.1255, 1.0)  # noqa: E731
+    G = G.cpu()
+    offsets = [(0, 0, 0, 0), (62, 5, 31, 30), (17, 30, 3, 8), (41, 12, 22, 29)]
+    for off in offsets:
+        assert sum(off) % 2 == 0
+        ub, idx = _block(u, off, n)
+        g_ref = md.gradient(fn, torch.as_tensor(np.ascontiguousarray(ub)))
+        inner = [ix[r:n - r] for ix in idx]
+        got = G[np.ix_(*inner)]
+        want = g_ref[r:n - r, r:n - r, r:n - r, r:n - r]
+        err = max_rel(got, want)
+        print(f"  {force} block at {off}: max rel err {err:.2e} over {want.numel() // 9} links", flush=True)
+        assert err < bar, off

@@ -6,7 +6,8 @@ R-algorithm trajectory and reunitarisation.
   coordinate-loop sum over plaquettes on a small lattice; gauge invariance.
 * Clover determinant: the closed form -8 Vh ln(1 - (kappa c_sw sin B)^2) of
   the flux field; gauge invariance; stationary at pure gauge.
-* Forces: central finite differences along su(3) generators.
+* Forces: central finite differences along su(3) generators; locality (the
+  force of a block cut out of a larger lattice is exact away from its edges).
 * Two-flavour identity: summing the pseudofermion force over a complete set
   of noise vectors (E[xi xi^dag] = 1) and adding the determinant force gives
   the force of -ln det(M^dag M) of the dense unpreconditioned operator.
@@ -146,6 +147,38 @@ def test_force_vs_fd(which):
     for site, mu, a in PICKS:
         fd = _fd_force(act, u, site, mu, a)
         assert abs(fd - float(f[site + (mu, a)])) < 1e-8 * max(1.0, scale), (which, site, mu, a, fd)
+
+
+@pytest.mark.parametrize("which", ["gauge", "det"])
+def test_forces_are_local(which):
+    """The gauge force on a link depends on the links within one site of it, the
+    determinant force on those within two: on an 8^4 lattice the force of an n^4
+    block cut out periodically (n = 4, 6) equals the whole lattice's at the links
+    whose block coordinates lie in [r, n - 1 - r] (r = 1, 2), for offsets with an
+    even coordinate sum (the block keeps the lattice's parity); one site less of
+    margin, or an odd offset for the determinant (even and odd sites swapped),
+    does not.  The GPU test at 32^3x64 samples the force this way."""
+    dims = (8, 8, 8, 8)
+    u = synth.random_su3_field(dims, 0.3, 1)
+    if which == "gauge":
+        act, n, r = (lambda v: md.gauge_action(v, 5.6)), 4, 1  # noqa: E731
+    else:
+        act, n, r = (lambda v: md.clover_det_action(v, 0.125, 1.0)), 6, 2  # noqa: E731
+    g_full = md.gradient(act, torch.as_tensor(u))
+
+    def block_err(off, margin):
+        idx = [(o + np.arange(n)) % e for o, e in zip(off, u.shape[:4])]
+        g = md.gradient(act, torch.as_tensor(np.ascontiguousarray(u[np.ix_(*idx)])))
+        inner = [ix[margin:n - margin] for ix in idx]
+        want = g_full[np.ix_(*inner)]
+        got = g[margin:n - margin, margin:n - margin, margin:n - margin, margin:n - margin]
+        return float(torch.abs(got - want).max() / torch.abs(want).max())
+
+    for off in [(0, 0, 0, 0), (6, 5, 7, 0), (3, 7, 1, 5), (7, 7, 7, 7)]:
+        assert block_err(off, r) < 1e-14, off
+    assert block_err((0, 0, 0, 0), r - 1) > 1e-2
+    if which == "det":
+        assert block_err((1, 0, 0, 0), r) > 1e-2
 
 
 @pytest.mark.slow
