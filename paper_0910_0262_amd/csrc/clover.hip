@@ -130,7 +130,7 @@ hipError_t launch_clover_build(const Geom& g, const double2* u18, double kappa, 
 // Hermitian positive-definite 6x6 inverse by Cholesky A = L L^dag:
 // A^{-1} = L^{-dag} L^{-1}, and ln det A = sum_j ln L_jj^2.  Returns false if
 // a pivot is not positive.
-__device__ bool invert_block(const Block<double>& a, Block<double>& inv, double& logdet) {
+__device__ __forceinline__ bool invert_block(const Block<double>& a, Block<double>& inv, double& logdet) {
   Cx<double> L[6][6];
   logdet = 0.0;
 #pragma unroll
@@ -196,23 +196,22 @@ __device__ void block_reals(const Block<double>& b, double r[36]) {
     r[7 + 2 * k] = b.o[k].im;
   }
 }
+// The 36 reals of one block in FP32, and their max |real|.
+__device__ __forceinline__ float block_reals32(const Block<double>& b, float r[36]) {
+  double rr[36];
+  block_reals(b, rr);
+  float m = 0.f;
+#pragma unroll
+  for (int k = 0; k < 36; ++k) {
+    r[k] = float(rr[k]);
+    m = fmaxf(m, fabsf(r[k]));
+  }
+  return m;
+}
 // FP32 copy: 18 float4 chunks, reals [b * 36 + r]; binary16 copy: 9 chunks of
 // 8 halves with a per-block float32 scale (max |real|).
-__device__ void store_site_low(const Block<double> blk[2], float4* f32, uint4* h16, float2* hs, int stride, int i) {
-  float r[72];
-  float sc[2];
-#pragma unroll
-  for (int b = 0; b < 2; ++b) {
-    double rr[36];
-    block_reals(blk[b], rr);
-    float m = 0.f;
-#pragma unroll
-    for (int k = 0; k < 36; ++k) {
-      r[36 * b + k] = float(rr[k]);
-      m = fmaxf(m, fabsf(r[36 * b + k]));
-    }
-    sc[b] = m;
-  }
+__device__ __forceinline__ void store_low(const float r[72], const float sc[2], float4* f32, uint4* h16, float2* hs,
+                                          int stride, int i) {
 #pragma unroll
   for (int k = 0; k < 18; ++k) f32[(size_t)k * stride + i] = make_float4(r[4 * k], r[4 * k + 1], r[4 * k + 2], r[4 * k + 3]);
   const float inv0 = sc[0] > 0.f ? 1.0f / sc[0] : 0.f, inv1 = sc[1] > 0.f ? 1.0f / sc[1] : 0.f;
@@ -229,6 +228,29 @@ __device__ void store_site_low(const Block<double> blk[2], float4* f32, uint4* h
   hs[i] = make_float2(sc[0], sc[1]);
 }
 
+// Odd-site block B: A_oo^{-1} in FP64 (zero if A is not positive definite)
+// and its reals in FP32 for the low-precision copies.  The two blocks go
+// through this one after the other with compile-time indices: a loop over
+// them indexed its arrays at run time, which put both blocks and both
+// inverses in scratch memory.
+template <int B>
+__device__ __forceinline__ bool invert_site_block(const CloverF64& co, int i, double2* clov_inv, int stride,
+                                                  float r[36], float& sc, double& ld) {
+  Block<double> a, inv;
+  load_block(co, i, B, a);
+  const bool ok = invert_block(a, inv, ld);
+  if (!ok) {
+    ld = 0.0;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) inv.d[k] = 0.0;
+#pragma unroll
+    for (int k = 0; k < 15; ++k) inv.o[k] = {0.0, 0.0};
+  }
+  store_block_f64(clov_inv + (size_t)(B * 18) * stride, stride, i, inv);
+  sc = block_reals32(inv, r);
+  return ok;
+}
+
 __global__ void __launch_bounds__(64) clover_invert_k(Geom g, const double2* __restrict__ clov,
                                                       double2* __restrict__ clov_inv, float4* clov32_e,
                                                       float4* clovinv32_o, uint4* clovh_e, float2* clovh_es,
@@ -237,30 +259,23 @@ __global__ void __launch_bounds__(64) clover_invert_k(Geom g, const double2* __r
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= g.Vh) return;
   const CloverF64 ce{clov, g.stride}, co{clov + (size_t)36 * g.stride, g.stride};
-  Block<double> a[2], inv[2];
-  // even sites: low-precision copies of A_ee
-  load_block(ce, i, 0, a[0]);
-  load_block(ce, i, 1, a[1]);
-  store_site_low(a, clov32_e, clovh_e, clovh_es, g.stride, i);
-  // odd sites: A_oo^{-1}
-  load_block(co, i, 0, a[0]);
-  load_block(co, i, 1, a[1]);
-  bool ok = true;
-  double ld_site = 0.0;
-#pragma unroll 1
-  for (int b = 0; b < 2; ++b) {
-    double ld = 0.0;
-    if (invert_block(a[b], inv[b], ld)) {
-      ld_site += ld;
-    } else {
-      ok = false;
-      for (int k = 0; k < 6; ++k) inv[b].d[k] = 0.0;
-      for (int k = 0; k < 15; ++k) inv[b].o[k] = {0.0, 0.0};
-    }
-    store_block_f64(clov_inv + (size_t)(b * 18) * g.stride, g.stride, i, inv[b]);
+  float r[72], sc[2];
+  {
+    // even sites: low-precision copies of A_ee
+    Block<double> a;
+    load_block(ce, i, 0, a);
+    sc[0] = block_reals32(a, r);
+    load_block(ce, i, 1, a);
+    sc[1] = block_reals32(a, r + 36);
+    store_low(r, sc, clov32_e, clovh_e, clovh_es, g.stride, i);
   }
-  store_site_low(inv, clovinv32_o, clovinvh_o, clovinvh_os, g.stride, i);
-  logdet[i] = ok ? ld_site : 0.0;
+  // odd sites: A_oo^{-1}
+  double ld0 = 0.0, ld1 = 0.0;
+  const bool ok0 = invert_site_block<0>(co, i, clov_inv, g.stride, r, sc[0], ld0);
+  const bool ok1 = invert_site_block<1>(co, i, clov_inv, g.stride, r + 36, sc[1], ld1);
+  store_low(r, sc, clovinv32_o, clovinvh_o, clovinvh_os, g.stride, i);
+  const bool ok = ok0 && ok1;
+  logdet[i] = ok ? ld0 + ld1 : 0.0;
   if (!ok) *status = 1;
 }
 
