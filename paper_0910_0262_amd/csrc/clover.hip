@@ -292,7 +292,7 @@ __global__ void __launch_bounds__(64) clover_compact_k(Geom g, const double2* __
   float r32[52];
   float sc[2];
   double dev = 0.0;
-#pragma unroll 1
+#pragma unroll
   for (int b = 0; b < 2; ++b) {
     Block<double> a;
     load_block(ce, i, b, a);
