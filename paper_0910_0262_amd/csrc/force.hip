@@ -179,11 +179,12 @@ template <bool FERM, bool DET>
 __global__ void __launch_bounds__(128) clover_xi_k(Geom g, SpF64 le, SpF64 lo, SpF64 re, SpF64 ro, double w_e,
                                                    double w_o, const double2* __restrict__ cinv, double w_det,
                                                    double2* __restrict__ xi) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= g.V) return;
-  int x[4];
-  lex_coords(i, g, x);
-  const int par = parity_of(x), cb = i >> 1;
+  // work-items 0 .. Vh - 1 take the even sites and Vh .. V - 1 the odd ones
+  // (by checkerboard index), so that a wavefront has one parity and the
+  // determinant part (odd sites only) runs on whole wavefronts
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= g.V) return;
+  const int par = t >= g.Vh ? 1 : 0, cb = t - par * g.Vh;
   Spinor<double> l, r;
   if constexpr (FERM) {
     load(par ? lo : le, cb, l);
