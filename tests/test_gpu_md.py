@@ -15,7 +15,7 @@ import oracle as O
 from oracle import md
 from paper_0910_0262_amd import Lattice, QCDError, capi, synth
 
-from ._gpu_helpers import max_rel, to_dev
+from ._gpu_helpers import max_rel, pack_blocks, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -235,3 +235,27 @@ def test_md_forces_full_lattice_sampled(full32, force):
         err = max_rel(got, want)
         print(f"  {force} block at {off}: max rel err {err:.2e} over {want.numel() // 9} links", flush=True)
         assert err < bar, off
+
+
+def test_clover_full_lattice_sampled(full32):
+    """The clover term of a site depends only on the links of its four leaves
+    (within one site of it), so the oracle's A on a 4^4 block cut out of the
+    32^3x64 lattice is exact at the block's sites with coordinates 1 and 2.
+    The library's A (all sites) and A^{-1} (odd sites), built in the launch
+    shape of that lattice, are compared there with it at the bars of the
+    small-lattice clover test (1e-14 / 1e-13 of the largest entry)."""
+    u, lat = full32
+    A, Ai = lat.get_clover()
+    A, Ai = A.cpu(), Ai.cpu()
+    lt, lz, ly, lx = u.shape[:4]
+    for off in [(0, 0, 0, 0), (62, 5, 31, 30), (17, 30, 3, 8), (41, 12, 22, 29)]:
+        ub, idx = _block(u, off, 4)
+        a = O.clover_matrix(torch.as_tensor(np.ascontiguousarray(ub)), 0.1255, 1.0)
+        a_in = a[1:3, 1:3, 1:3, 1:3].reshape(-1, 12, 12)
+        t, z, y, x = (c.reshape(-1) for c in np.meshgrid(*[ix[1:3] for ix in idx], indexing="ij"))
+        site = x + lx * (y + ly * (z + lz * t))
+        odd = (x + y + z + t) % 2 == 1
+        err_a = max_rel(A[site], pack_blocks(a_in))
+        err_i = max_rel(Ai[site[odd] // 2], pack_blocks(torch.linalg.inv(a_in[odd])))
+        print(f"  clover block at {off}: A {err_a:.2e}, A_oo^-1 {err_i:.2e} over {len(site)} sites", flush=True)
+        assert err_a < 1e-14 and err_i < 1e-13, off

@@ -90,3 +90,21 @@ def test_clover_vanishes_when_csw_zero():
     u = torch.as_tensor(synth.random_su3_field((4, 4, 4, 4), 0.3, 0))
     a = O.clover_matrix(u, 0.12, 0.0)
     assert torch.equal(a, torch.eye(12, dtype=C).expand_as(a))
+
+
+def test_clover_is_local():
+    """A(x) depends only on the links of the four leaves around x: on an 8^4
+    lattice the clover of a 4^4 block cut out periodically equals the whole
+    lattice's at the block's sites with coordinates 1 and 2, and not at its
+    edge sites (whose leaves wrap around the block).  The GPU test at 32^3x64
+    samples the clover this way."""
+    dims = (8, 8, 8, 8)
+    u = synth.random_su3_field(dims, 0.3, 2)
+    a_full = O.clover_matrix(torch.as_tensor(u), 0.125, 1.0)
+    for off in [(0, 0, 0, 0), (6, 5, 7, 0), (3, 7, 1, 5)]:
+        idx = [(o + np.arange(4)) % e for o, e in zip(off, u.shape[:4])]
+        a = O.clover_matrix(torch.as_tensor(np.ascontiguousarray(u[np.ix_(*idx)])), 0.125, 1.0)
+        inner = a_full[np.ix_(*[ix[1:3] for ix in idx])]
+        assert float(torch.abs(a[1:3, 1:3, 1:3, 1:3] - inner).max()) < 1e-15, off
+        edge = a_full[np.ix_(*idx)]
+        assert float(torch.abs(a - edge).max()) > 1e-3
