@@ -284,9 +284,12 @@ __global__ void __launch_bounds__(64) force_clover_k(Geom g, const double2* __re
   if (!md_link(g, mu, i, y)) return;
   const int par = parity_of(y), cb = i >> 1;
   Mat<double> mt = mzero<double>();
+  // planes in the order nu = mu ^ s: at each step the four directions of a
+  // site pair up on two planes, whose Xi and links the two wavefronts of a
+  // pair gather at about the same time
 #pragma unroll 1
-  for (int nu = 0; nu < 4; ++nu) {
-    if (nu == mu) continue;
+  for (int s = 1; s < 4; ++s) {
+    const int nu = mu ^ s;
     const int p = mu < nu ? plane_index(mu, nu) : plane_index(nu, mu);
     int ypm[4], ypn[4], ymn[4], ypmpn[4], ypmmn[4];
     shift4(g, y, mu, 1, ypm);
