@@ -1236,7 +1236,7 @@ int qcd_solve_multi(qcd_ctx* c, const qcd_solver_params* p, int n_rhs, const voi
 // The fermion part of the force enters with weight wf; with det the
 // derivative of -2 sum_odd ln det A, also weighted wf, joins the clover part.
 static int force_core(qcd_ctx* c, const qcd_solver_params* p, double* S, CgCounters& cnt, int* conv_rc,
-                      double wf = 1.0, bool det = false) {
+                      double wf = 1.0, bool det = false, double gauge_coef = 0.0) {
   const Geom& g = c->g;
   const int nb = nblocks(c);
   if (!c->xi) QCHK(dalloc(&c->xi, (size_t)2 * 6 * 9 * g.stride * sizeof(double2)));
@@ -1271,7 +1271,7 @@ static int force_core(qcd_ctx* c, const qcd_solver_params* p, double* S, CgCount
   if (c->csw != 0.0) {
     HIPCHK(launch_clover_xi(g, c->f64(V_Y), c->f64(V_W), c->f64(V_X), c->f64(V_Z), wf, wf * k2,
                             det ? c->clov_inv : nullptr, wf, c->xi, c->stream));
-    HIPCHK(launch_force_clover(g, c->u18, c->xi, 0.5 * c->kappa * c->csw, c->gint, c->stream));
+    HIPCHK(launch_force_clover(g, c->u18, c->xi, 0.5 * c->kappa * c->csw, c->gint, c->stream, gauge_coef));
   }
   return QCD_OK;
 }
@@ -1466,14 +1466,18 @@ int qcd_md_trajectory(qcd_ctx* c, const qcd_md_params* md, void* U_dev, double* 
     }
     if (md->beta != 0.0) QCHK(gauge_action_sync(c, md->beta, &s_g));
     if (det) QCHK(det_action_sync(c, &s_d));
+    // with a clover force pass the gauge force is added there (its staples
+    // are products that pass forms anyway); otherwise it has its own launch
+    const bool gauge_fused = ferm && c->csw != 0.0 && md->beta != 0.0;
     if (ferm) {
       int conv = QCD_OK;
-      QCHK(force_core(c, p, &s_f, cnt, &conv, wf, det));
+      QCHK(force_core(c, p, &s_f, cnt, &conv, wf, det, gauge_fused ? -md->beta / 3.0 : 0.0));
       if (conv != QCD_OK) conv_all = conv;
     } else {
       HIPCHK(launch_force_zero(g, c->gint, c->stream));
     }
-    if (md->beta != 0.0) HIPCHK(launch_gauge_force(g, c->u18, -md->beta / 3.0, 1, c->gint, c->stream));
+    if (md->beta != 0.0 && !gauge_fused)
+      HIPCHK(launch_gauge_force(g, c->u18, -md->beta / 3.0, 1, c->gint, c->stream));
     HIPCHK(launch_force_out(g, c->u18, c->gint, nullptr, c->fbuf, c->stream));
     HIPCHK(launch_mom_update(g, P_dev, c->fbuf, dt, c->stream));
     QCHK(move_links(c, P_dev, 0.5 * dt, md->reunitarize == 1));

@@ -263,7 +263,8 @@ __device__ __forceinline__ Mat<double> xi_at(const double2* xi, const Geom& g, i
 // The factors are fetched by the callables in the order they are needed,
 // which keeps at most four 3x3 matrices live.
 template <class F1, class F2, class F3, class G0, class G1, class G2, class G3>
-__device__ __forceinline__ Mat<double> insertion(F1 l1, F2 l2, F3 l3, G0 c0, G1 c1, G2 c2, G3 c3) {
+__device__ __forceinline__ Mat<double> insertion(F1 l1, F2 l2, F3 l3, G0 c0, G1 c1, G2 c2, G3 c3,
+                                                 Mat<double>* staple = nullptr) {
   Mat<double> A, T;
   {
     const Mat<double> L2 = l2(), L3 = l3();
@@ -274,16 +275,24 @@ __device__ __forceinline__ Mat<double> insertion(F1 l1, F2 l2, F3 l3, G0 c0, G1 
   T = madd(T, mm(c2(), A));
   const Mat<double> L1 = l1();
   Mat<double> m = mm(L1, T);
-  return madd(m, mm(c1(), mm(L1, A)));
+  const Mat<double> st = mm(L1, A);  // L1 L2 L3: the plaquette without the link, a staple of the gauge force
+  if (staple) *staple = st;
+  return madd(m, mm(c1(), st));
 }
 
+// GAUGE: the products L1 L2 L3 of the two insertions of a plane are the
+// up staple and the adjoint of the down staple of the Wilson gauge force
+// (or the reverse), so that force is added here too, with weight coef_g, as
+// gauge_force_k would add it.
+template <bool GAUGE>
 __global__ void __launch_bounds__(64) force_clover_k(Geom g, const double2* __restrict__ u18,
-                                                     const double2* __restrict__ xi, double coef,
+                                                     const double2* __restrict__ xi, double coef, double coef_g,
                                                      double2* __restrict__ gint) {
   int mu, i, y[4];
   if (!md_link(g, mu, i, y)) return;
   const int par = parity_of(y), cb = i >> 1;
   Mat<double> mt = mzero<double>();
+  Mat<double> st = mzero<double>();  // staple sum (GAUGE)
   // planes in the order nu = mu ^ s: at each step the four directions of a
   // site pair up on two planes, whose Xi and links the two wavefronts of a
   // pair gather at about the same time
@@ -300,28 +309,31 @@ __global__ void __launch_bounds__(64) force_clover_k(Geom g, const double2* __re
     auto U = [&](int d, const int* c) { return u_at(u18, g, d, c); };
     auto Ud = [&](int d, const int* c) { return adj(u_at(u18, g, d, c)); };
     auto X = [&](const int* c) { return xi_at(xi, g, p, c); };
-    Mat<double> mu_, md;
+    Mat<double> mu_, md, s1, s2;
+    Mat<double>* const p1 = GAUGE ? &s1 : nullptr;
+    Mat<double>* const p2 = GAUGE ? &s2 : nullptr;
     if (mu < nu) {
-      // link first in the plaquette at y (mu then nu)
+      // link first in the plaquette at y (mu then nu); s1 = up staple
       mu_ = insertion([&] { return U(nu, ypm); }, [&] { return Ud(mu, ypn); }, [&] { return Ud(nu, y); },
                       [&] { return X(y); }, [&] { return X(ypm); }, [&] { return X(ypmpn); },
-                      [&] { return X(ypn); });
-      // link reversed (third) in the plaquette at y - nu
+                      [&] { return X(ypn); }, p1);
+      // link reversed (third) in the plaquette at y - nu; s2 = down staple^dag
       md = insertion([&] { return Ud(nu, ymn); }, [&] { return U(mu, ymn); }, [&] { return U(nu, ypmmn); },
                      [&] { return X(ypm); }, [&] { return X(y); }, [&] { return X(ymn); },
-                     [&] { return X(ypmmn); });
+                     [&] { return X(ypmmn); }, p2);
     } else {
-      // plane (nu, mu): link second in the plaquette at y - nu
+      // plane (nu, mu): link second in the plaquette at y - nu; s1 = down staple
       mu_ = insertion([&] { return Ud(nu, ypmmn); }, [&] { return Ud(mu, ymn); }, [&] { return U(nu, ymn); },
                       [&] { return X(y); }, [&] { return X(ypm); }, [&] { return X(ypmmn); },
-                      [&] { return X(ymn); });
-      // link reversed (fourth) in the plaquette at y
+                      [&] { return X(ymn); }, p1);
+      // link reversed (fourth) in the plaquette at y; s2 = up staple^dag
       md = insertion([&] { return U(nu, y); }, [&] { return U(mu, ypn); }, [&] { return Ud(nu, ypm); },
                      [&] { return X(ypm); }, [&] { return X(y); }, [&] { return X(ypn); },
-                     [&] { return X(ypmpn); });
+                     [&] { return X(ypmpn); }, p2);
     }
     // reversed occurrences: Im tr(dU^dag M) = -Im tr(dU M^dag)
     mt = madd(mt, msub(mu_, adj(md)));
+    if constexpr (GAUGE) st = madd(st, madd(s1, adj(s2)));
   }
   // dS = coef Im tr(dU mt)  =>  G = coef * i * mt^dag
   double2* base = gint + (size_t)((mu * 2 + par) * 9) * g.stride;
@@ -330,12 +342,21 @@ __global__ void __launch_bounds__(64) force_clover_k(Geom g, const double2* __re
   for (int r = 0; r < 3; ++r)
 #pragma unroll
     for (int c = 0; c < 3; ++c) gm.m[r][c] = gm.m[r][c] + coef * ti(conj(mt.m[c][r]));
+  if constexpr (GAUGE) {
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) gm.m[r][c] = gm.m[r][c] + coef_g * conj(st.m[c][r]);
+  }
   store_mat(base, g.stride, cb, gm);
 }
 
 hipError_t launch_force_clover(const Geom& g, const double2* u18, const double2* xi, double coef, double2* gint,
-                               hipStream_t s) {
-  hipLaunchKernelGGL(force_clover_k, dim3(md_link_blocks(g)), dim3(64), 0, s, g, u18, xi, coef, gint);
+                               hipStream_t s, double coef_g) {
+  if (coef_g != 0.0)
+    hipLaunchKernelGGL(force_clover_k<true>, dim3(md_link_blocks(g)), dim3(64), 0, s, g, u18, xi, coef, coef_g, gint);
+  else
+    hipLaunchKernelGGL(force_clover_k<false>, dim3(md_link_blocks(g)), dim3(64), 0, s, g, u18, xi, coef, 0.0, gint);
   return hipGetLastError();
 }
 

@@ -223,8 +223,9 @@ hipError_t launch_force_hop(const Geom& g, const double2* u18, SpF64 ell_e, SpF6
 // ell_e.p == nullptr drops the fermion term; cinv == nullptr the determinant term
 hipError_t launch_clover_xi(const Geom& g, SpF64 ell_e, SpF64 ell_o, SpF64 rho_e, SpF64 rho_o, double w_e,
                             double w_o, const double2* cinv, double w_det, double2* xi, hipStream_t s);
+// coef_g != 0 adds the Wilson gauge force (weight coef_g, as launch_gauge_force) in the same pass
 hipError_t launch_force_clover(const Geom& g, const double2* u18, const double2* xi, double coef, double2* gint,
-                               hipStream_t s);
+                               hipStream_t s, double coef_g = 0.0);
 hipError_t launch_force_out(const Geom& g, const double2* u18, const double2* gint, double2* g_user,
                             double* f_user, hipStream_t s);
 hipError_t launch_gauge_force(const Geom& g, const double2* u18, double coef, int accumulate, double2* gint,
